@@ -1,0 +1,613 @@
+/*
+ * Plain CPU oracle of the upwind Gauss-Lobatto-collocation DG advection
+ * operator and its low-storage Runge-Kutta integrator. TEST INFRASTRUCTURE
+ * ONLY: used by tests/, the smoke check and the benchmark's CPU baseline,
+ * never by the product library. It is deliberately slow: it evaluates the
+ * d-dimensional basis functions and their gradients directly at the
+ * quadrature points and forms the weak-form sums as written, with no sum
+ * factorization. See oracle.h for the paper passages each part follows.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_MAXD 6
+#define OR_MAXK 8
+#define OR_MAXN (OR_MAXK + 1)
+
+static const double OR_PI = 3.14159265358979323846264338327950288;
+
+/* ------------------------------------------------------------------------ */
+/* 1D Gauss-Lobatto rule (Sec. 2.3 nodes, Sec. 2.5 quadrature)              */
+/* ------------------------------------------------------------------------ */
+
+/* Legendre P_k(s) and P_k'(s) from the three-term recurrence
+ * m P_m = (2m-1) s P_{m-1} - (m-1) P_{m-2} and P_m' = s P_{m-1}' + m P_{m-1}. */
+static void legendre(int k, double s, double *p, double *dp) {
+  double pm1 = 1.0, dpm1 = 0.0; /* P_0, P_0' */
+  double pm = s, dpm = 1.0;     /* P_1, P_1' */
+  if (k == 0) {
+    *p = 1.0;
+    *dp = 0.0;
+    return;
+  }
+  for (int m = 2; m <= k; ++m) {
+    double pn = ((2.0 * m - 1.0) * s * pm - (m - 1.0) * pm1) / m;
+    double dpn = s * dpm + m * pm;
+    pm1 = pm;
+    dpm1 = dpm;
+    pm = pn;
+    dpm = dpn;
+  }
+  (void)dpm1;
+  *p = pm;
+  *dp = dpm;
+}
+
+int or_gl_rule(int k, double *xi, double *w) {
+  if (k < 1 || k > 16) return -1;
+  /* Interior points: roots of P_k' on (-1,1), by Newton's method started at
+   * the Chebyshev-Gauss-Lobatto points; P_k'' from Legendre's equation
+   * (1-s^2) P'' = 2 s P' - k(k+1) P. */
+  double s[17];
+  s[0] = -1.0;
+  s[k] = 1.0;
+  for (int m = 1; m < k; ++m) {
+    double x = -cos(OR_PI * m / k);
+    for (int it = 0; it < 100; ++it) {
+      double p, dp;
+      legendre(k, x, &p, &dp);
+      double ddp = (2.0 * x * dp - k * (k + 1.0) * p) / (1.0 - x * x);
+      double dx = dp / ddp;
+      x -= dx;
+      if (fabs(dx) < 1e-16) break;
+    }
+    s[m] = x;
+  }
+  /* Weights on [-1,1]: 2 / (k(k+1) P_k(s_m)^2); halved for [0,1]. */
+  for (int m = 0; m <= k; ++m) {
+    double p, dp;
+    legendre(k, s[m], &p, &dp);
+    xi[m] = 0.5 * (1.0 + s[m]);
+    w[m] = 1.0 / (k * (k + 1.0) * p * p);
+  }
+  xi[0] = 0.0;
+  xi[k] = 1.0;
+  return 0;
+}
+
+/* l_m(x) = prod_{r != m} (x - xi_r) / (xi_m - xi_r). */
+double or_lagrange(int k, const double *xi, int m, double x) {
+  double v = 1.0;
+  for (int r = 0; r <= k; ++r)
+    if (r != m) v *= (x - xi[r]) / (xi[m] - xi[r]);
+  return v;
+}
+
+/* l_m'(x) = sum_{s != m} 1/(xi_m - xi_s) prod_{r != m, s} (x - xi_r)/(xi_m - xi_r). */
+double or_lagrange_deriv(int k, const double *xi, int m, double x) {
+  double sum = 0.0;
+  for (int s = 0; s <= k; ++s) {
+    if (s == m) continue;
+    double t = 1.0 / (xi[m] - xi[s]);
+    for (int r = 0; r <= k; ++r)
+      if (r != m && r != s) t *= (x - xi[r]) / (xi[m] - xi[r]);
+    sum += t;
+  }
+  return sum;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mesh bookkeeping (Sec. 3.1: the cells are pairs of x- and v-cells)        */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int d, dx, dv, n, k;
+  int64_t nd;     /* nodes per cell, n^d */
+  int64_t ncells; /* prod cells */
+  int cells[OR_MAXD];
+  int64_t cstride[OR_MAXD]; /* cell index stride per dim (dim 1 fastest) */
+  int64_t nstride[OR_MAXD]; /* node index stride per dim */
+  double lo[OR_MAXD], hi[OR_MAXD], h[OR_MAXD];
+  double xi[OR_MAXN], w[OR_MAXN];
+  double L[OR_MAXN][OR_MAXN];  /* L[m][q] = l_m(xi_q) */
+  double DL[OR_MAXN][OR_MAXN]; /* DL[m][q] = l_m'(xi_q) */
+  double M1[OR_MAXN];          /* diagonal of the 1D reference mass matrix */
+} or_geom;
+
+static int setup_geom(const or_mesh *mesh, int k, or_geom *g) {
+  if (!mesh) return -1;
+  if (mesh->dim_x < 1 || mesh->dim_x > 3 || mesh->dim_v < 1 || mesh->dim_v > 3)
+    return -1;
+  if (k < 1 || k > OR_MAXK) return -1;
+  memset(g, 0, sizeof(*g));
+  g->dx = mesh->dim_x;
+  g->dv = mesh->dim_v;
+  g->d = g->dx + g->dv;
+  g->k = k;
+  g->n = k + 1;
+  g->nd = 1;
+  g->ncells = 1;
+  for (int j = 0; j < g->d; ++j) {
+    if (mesh->cells[j] < 1 || !(mesh->hi[j] > mesh->lo[j])) return -1;
+    g->cells[j] = mesh->cells[j];
+    g->cstride[j] = g->ncells;
+    g->nstride[j] = g->nd;
+    g->ncells *= mesh->cells[j];
+    g->nd *= g->n;
+    g->lo[j] = mesh->lo[j];
+    g->hi[j] = mesh->hi[j];
+    g->h[j] = (mesh->hi[j] - mesh->lo[j]) / mesh->cells[j];
+  }
+  if (or_gl_rule(k, g->xi, g->w)) return -1;
+  for (int m = 0; m <= k; ++m)
+    for (int q = 0; q <= k; ++q) {
+      g->L[m][q] = or_lagrange(k, g->xi, m, g->xi[q]);
+      g->DL[m][q] = or_lagrange_deriv(k, g->xi, m, g->xi[q]);
+    }
+  /* 1D reference mass matrix M1[a][b] = sum_q w_q l_a(xi_q) l_b(xi_q). The
+   * d-dimensional cell mass matrix with tensor quadrature is the Kronecker
+   * product of these (times prod h_j), so it is diagonal exactly when M1
+   * is: the collocation property of Sec. 1.3. Refuse to proceed otherwise. */
+  for (int a = 0; a <= k; ++a)
+    for (int b = 0; b <= k; ++b) {
+      double m = 0.0;
+      for (int q = 0; q <= k; ++q) m += g->w[q] * g->L[a][q] * g->L[b][q];
+      if (a == b)
+        g->M1[a] = m;
+      else if (fabs(m) > 1e-14)
+        return -1;
+    }
+  return 0;
+}
+
+static void cell_multi(const or_geom *g, int64_t c, int *cm) {
+  for (int j = 0; j < g->d; ++j) cm[j] = (int)((c / g->cstride[j]) % g->cells[j]);
+}
+static void node_multi(const or_geom *g, int64_t q, int *qm) {
+  for (int j = 0; j < g->d; ++j) qm[j] = (int)((q / g->nstride[j]) % g->n);
+}
+static int64_t cell_linear(const or_geom *g, const int *cm) {
+  int64_t c = 0;
+  for (int j = 0; j < g->d; ++j) c += cm[j] * g->cstride[j];
+  return c;
+}
+static int64_t node_linear(const or_geom *g, const int *qm) {
+  int64_t q = 0;
+  for (int j = 0; j < g->d; ++j) q += qm[j] * g->nstride[j];
+  return q;
+}
+
+/* Periodic neighbour of cell cm across dim j in direction dir (+1/-1). */
+static int64_t neighbour_cell(const or_geom *g, const int *cm, int j, int dir) {
+  int nm[OR_MAXD];
+  for (int m = 0; m < g->d; ++m) nm[m] = cm[m];
+  nm[j] = (cm[j] + dir + g->cells[j]) % g->cells[j];
+  return cell_linear(g, nm);
+}
+
+/* Physical coordinate of node qm of cell cm in dim j. */
+static double node_coord(const or_geom *g, const int *cm, const int *qm, int j) {
+  return g->lo[j] + (cm[j] + g->xi[qm[j]]) * g->h[j];
+}
+
+/* Advection field component j at node qm of cell cm (Sec. 6.1: v from the
+ * velocity node, E from the table at the configuration node). */
+static double field_at(const or_geom *g, const or_field *f, const int *cm,
+                       const int *qm, int j) {
+  if (f->kind == 0) return f->a[j];
+  if (j < g->dx) return node_coord(g, cm, qm, g->dx + j);
+  int64_t xcell = 0, xs = 1, xnode = 0, ns = 1;
+  for (int m = 0; m < g->dx; ++m) {
+    xcell += cm[m] * xs;
+    xs *= g->cells[m];
+    xnode += qm[m] * ns;
+    ns *= g->n;
+  }
+  int64_t nxn = ns;
+  return f->sign * f->E[((xcell * nxn) + xnode) * g->dx + (j - g->dx)];
+}
+
+static int check_field(const or_geom *g, const or_field *f) {
+  if (!f) return -1;
+  if (f->kind == 0) return 0;
+  if (f->kind == 1) return (g->dx == g->dv && f->E) ? 0 : -1;
+  return -1;
+}
+
+int64_t or_num_dofs(const or_mesh *mesh, int k) {
+  or_geom g;
+  if (setup_geom(mesh, k, &g)) return -1;
+  return g.nd * g.ncells;
+}
+
+int or_node_coords(const or_mesh *mesh, int k, double *X) {
+  or_geom g;
+  if (setup_geom(mesh, k, &g)) return -1;
+#pragma omp parallel for schedule(static)
+  for (int64_t c = 0; c < g.ncells; ++c) {
+    int cm[OR_MAXD], qm[OR_MAXD];
+    cell_multi(&g, c, cm);
+    for (int64_t q = 0; q < g.nd; ++q) {
+      node_multi(&g, q, qm);
+      for (int j = 0; j < g.d; ++j)
+        X[(c * g.nd + q) * g.d + j] = node_coord(&g, cm, qm, j);
+    }
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The operator M^{-1} A(u) on one cell (Algorithm 2, Sec. 1.3 weak form)   */
+/* ------------------------------------------------------------------------ */
+
+/* phi_i at the node qm of the own cell: prod_m l_{i_m}(xi_{q_m}). */
+static double phi_at(const or_geom *g, const int *im, const int *qm) {
+  double v = 1.0;
+  for (int m = 0; m < g->d; ++m) v *= g->L[im[m]][qm[m]];
+  return v;
+}
+
+/* d/dx_j phi_i at node qm: l'_{i_j}(xi_{q_j}) / h_j * prod_{m != j} l_{i_m}(xi_{q_m}). */
+static double dphi_at(const or_geom *g, const int *im, const int *qm, int j) {
+  double v = g->DL[im[j]][qm[j]] / g->h[j];
+  for (int m = 0; m < g->d; ++m)
+    if (m != j) v *= g->L[im[m]][qm[m]];
+  return v;
+}
+
+/* Volume quadrature weight W_q = prod_j h_j w_{q_j}. */
+static double vol_weight(const or_geom *g, const int *qm) {
+  double v = 1.0;
+  for (int m = 0; m < g->d; ++m) v *= g->h[m] * g->w[qm[m]];
+  return v;
+}
+
+/* Face quadrature weight on a face normal to dim j: prod_{m != j} h_m w_{q_m}. */
+static double face_weight(const or_geom *g, const int *qm, int j) {
+  double v = 1.0;
+  for (int m = 0; m < g->d; ++m)
+    if (m != j) v *= g->h[m] * g->w[qm[m]];
+  return v;
+}
+
+/* Scratch for one cell evaluation. */
+typedef struct {
+  double *uh;   /* u_h at the quadrature points of the cell */
+  double *rhs;  /* V - F, then divided by the mass diagonal */
+  double *acell; /* a_j at each node: acell[q * d + j] */
+} or_scratch;
+
+static void eval_cell(const or_geom *g, const or_field *f, int mode,
+                      const double *u, int64_t c, double *out, or_scratch *s) {
+  const int d = g->d, k = g->k;
+  const int64_t nd = g->nd;
+  int cm[OR_MAXD], im[OR_MAXD], qm[OR_MAXD], pm[OR_MAXD];
+  cell_multi(g, c, cm);
+  const double *uc = u + c * nd;
+
+  for (int64_t q = 0; q < nd; ++q) {
+    node_multi(g, q, qm);
+    for (int j = 0; j < d; ++j) s->acell[q * d + j] = field_at(g, f, cm, qm, j);
+  }
+
+  /* Step 2 of Algorithm 2, interpolation: u_h(x_q) = sum_i' u_i' phi_i'(x_q). */
+  for (int64_t q = 0; q < nd; ++q) {
+    node_multi(g, q, qm);
+    double v = 0.0;
+    if (mode == 0) {
+      for (int64_t ip = 0; ip < nd; ++ip) {
+        node_multi(g, ip, im);
+        v += uc[ip] * phi_at(g, im, qm);
+      }
+    } else {
+      /* Only phi_q is nonzero at x_q (nodal basis, collocated points). */
+      v = uc[q] * phi_at(g, qm, qm);
+    }
+    s->uh[q] = v;
+  }
+
+  /* Volume term V_i = sum_q W_q grad phi_i(x_q) . a(x_q) u_h(x_q). */
+  for (int64_t i = 0; i < nd; ++i) {
+    node_multi(g, i, im);
+    double v = 0.0;
+    if (mode == 0) {
+      for (int64_t q = 0; q < nd; ++q) {
+        node_multi(g, q, qm);
+        double W = vol_weight(g, qm);
+        for (int j = 0; j < d; ++j)
+          v += W * dphi_at(g, im, qm, j) * s->acell[q * d + j] * s->uh[q];
+      }
+    } else {
+      /* d/dx_j phi_i vanishes at x_q unless q agrees with i off dim j. */
+      for (int j = 0; j < d; ++j)
+        for (int r = 0; r <= k; ++r) {
+          for (int m = 0; m < d; ++m) qm[m] = im[m];
+          qm[j] = r;
+          int64_t q = node_linear(g, qm);
+          v += vol_weight(g, qm) * dphi_at(g, im, qm, j) * s->acell[q * d + j] *
+               s->uh[q];
+        }
+    }
+    s->rhs[i] = v;
+  }
+
+  /* Face term F_i = sum_faces sum_p W^f_p phi_i(x_p) (a.n) u*(x_p), upwind:
+   * u* is the own trace where a.n >= 0 (outflow), else the neighbour's. */
+  for (int j = 0; j < d; ++j)
+    for (int side = 0; side < 2; ++side) {
+      const int pj = side ? k : 0;        /* own node index on this face */
+      const int oj = side ? 0 : k;        /* neighbour's node index there */
+      const double nj = side ? 1.0 : -1.0; /* outward normal component */
+      const int64_t cn = neighbour_cell(g, cm, j, side ? +1 : -1);
+      const double *un = u + cn * nd;
+      for (int64_t p = 0; p < nd; ++p) {
+        node_multi(g, p, pm);
+        if (pm[j] != pj) continue; /* face points: nodes with q_j on the face */
+        double uown, unbr;
+        if (mode == 0) {
+          uown = 0.0;
+          unbr = 0.0;
+          for (int64_t ip = 0; ip < nd; ++ip) {
+            node_multi(g, ip, im);
+            uown += uc[ip] * phi_at(g, im, pm);
+            /* The neighbour's reference coordinates of x_p: the same in
+             * every dim but j, where x_p lies on its opposite face. */
+            double ph = 1.0;
+            for (int m = 0; m < d; ++m)
+              ph *= (m == j) ? g->L[im[m]][oj] : g->L[im[m]][pm[m]];
+            unbr += un[ip] * ph;
+          }
+        } else {
+          for (int m = 0; m < d; ++m) im[m] = pm[m];
+          uown = uc[p] * phi_at(g, pm, pm);
+          im[j] = oj;
+          double ph = 1.0;
+          for (int m = 0; m < d; ++m)
+            ph *= (m == j) ? g->L[oj][oj] : g->L[pm[m]][pm[m]];
+          unbr = un[node_linear(g, im)] * ph;
+        }
+        const double an = s->acell[p * d + j] * nj;
+        const double ustar = (an >= 0.0) ? uown : unbr;
+        const double Wf = face_weight(g, pm, j);
+        if (mode == 0) {
+          for (int64_t i = 0; i < nd; ++i) {
+            node_multi(g, i, im);
+            s->rhs[i] -= Wf * phi_at(g, im, pm) * an * ustar;
+          }
+        } else {
+          /* Only phi_p is nonzero at the node x_p. */
+          s->rhs[p] -= Wf * phi_at(g, pm, pm) * an * ustar;
+        }
+      }
+    }
+
+  /* Step 4, inverse mass: the diagonal prod_j h_j M1[i_j]. */
+  for (int64_t i = 0; i < nd; ++i) {
+    node_multi(g, i, im);
+    double m = 1.0;
+    for (int j = 0; j < d; ++j) m *= g->h[j] * g->M1[im[j]];
+    out[i] = s->rhs[i] / m;
+  }
+}
+
+int or_apply_cells(const or_mesh *mesh, int k, const or_field *field, int mode,
+                   const double *u, const int64_t *cells, int64_t ncells,
+                   double *out) {
+  or_geom g;
+  if (setup_geom(mesh, k, &g) || check_field(&g, field)) return -1;
+  if (mode != 0 && mode != 1) return -1;
+  for (int64_t t = 0; t < ncells; ++t)
+    if (cells[t] < 0 || cells[t] >= g.ncells) return -1;
+  int err = 0;
+#pragma omp parallel
+  {
+    or_scratch s;
+    s.uh = (double *)malloc(sizeof(double) * g.nd);
+    s.rhs = (double *)malloc(sizeof(double) * g.nd);
+    s.acell = (double *)malloc(sizeof(double) * g.nd * g.d);
+    if (!s.uh || !s.rhs || !s.acell) {
+#pragma omp atomic write
+      err = 1;
+    } else {
+#pragma omp for schedule(dynamic, 4)
+      for (int64_t t = 0; t < ncells; ++t)
+        eval_cell(&g, field, mode, u, cells[t], out + t * g.nd, &s);
+    }
+    free(s.uh);
+    free(s.rhs);
+    free(s.acell);
+  }
+  return err ? -1 : 0;
+}
+
+int or_apply(const or_mesh *mesh, int k, const or_field *field, int mode,
+             const double *u, double *out) {
+  or_geom g;
+  if (setup_geom(mesh, k, &g)) return -1;
+  int64_t *cells = (int64_t *)malloc(sizeof(int64_t) * g.ncells);
+  if (!cells) return -1;
+  for (int64_t c = 0; c < g.ncells; ++c) cells[c] = c;
+  int r = or_apply_cells(mesh, k, field, mode, u, cells, g.ncells, out);
+  free(cells);
+  return r;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Low-storage Runge-Kutta (Sec. 5.4: order 4, 5 stages, 3 vectors)         */
+/* ------------------------------------------------------------------------ */
+
+/* Carpenter & Kennedy (1994), five-stage fourth-order 2N-storage scheme:
+ * per stage  du <- A_s du + dt L(u),  u <- u + B_s du. */
+void or_lsrk45_coefficients(double *A, double *B, double *C) {
+  A[0] = 0.0;
+  A[1] = -567301805773.0 / 1357537059087.0;
+  A[2] = -2404267990393.0 / 2016746695238.0;
+  A[3] = -3550918686646.0 / 2091501179385.0;
+  A[4] = -1275806237668.0 / 842570457699.0;
+  B[0] = 1432997174477.0 / 9575080441755.0;
+  B[1] = 5161836677717.0 / 13612068292357.0;
+  B[2] = 1720146321549.0 / 2090206949498.0;
+  B[3] = 3134564353537.0 / 4481467310338.0;
+  B[4] = 2277821191437.0 / 14882151754819.0;
+  C[0] = 0.0;
+  C[1] = 1432997174477.0 / 9575080441755.0;
+  C[2] = 2526269341429.0 / 6820363962896.0;
+  C[3] = 2006345519317.0 / 3224310063776.0;
+  C[4] = 2802321613138.0 / 2924317926251.0;
+}
+
+int or_rk_steps(const or_mesh *mesh, int k, const or_field *field, int mode,
+                double dt, int nsteps, double *u) {
+  or_geom g;
+  if (setup_geom(mesh, k, &g) || check_field(&g, field)) return -1;
+  const int64_t N = g.nd * g.ncells;
+  double A[5], B[5], C[5];
+  or_lsrk45_coefficients(A, B, C);
+  double *du = (double *)calloc((size_t)N, sizeof(double));
+  double *L = (double *)malloc(sizeof(double) * (size_t)N);
+  if (!du || !L) {
+    free(du);
+    free(L);
+    return -1;
+  }
+  int r = 0;
+  for (int step = 0; step < nsteps && !r; ++step)
+    for (int st = 0; st < 5 && !r; ++st) {
+      r = or_apply(mesh, k, field, mode, u, L);
+      if (r) break;
+#pragma omp parallel for schedule(static)
+      for (int64_t i = 0; i < N; ++i) {
+        du[i] = A[st] * du[i] + dt * L[i];
+        u[i] = u[i] + B[st] * du[i];
+      }
+    }
+  free(du);
+  free(L);
+  return r;
+}
+
+double or_stable_dt(const or_mesh *mesh, int k, const or_field *field,
+                    double cfl) {
+  or_geom g;
+  if (setup_geom(mesh, k, &g) || check_field(&g, field)) return -1.0;
+  double sum = 0.0;
+  for (int j = 0; j < g.d; ++j) {
+    double amax = 0.0;
+    if (field->kind == 0) {
+      amax = fabs(field->a[j]);
+    } else if (j < g.dx) {
+      /* |v_j| is largest at a node of the velocity mesh. */
+      const int vj = g.dx + j;
+      for (int c = 0; c < g.cells[vj]; ++c)
+        for (int q = 0; q <= k; ++q) {
+          double v = g.lo[vj] + (c + g.xi[q]) * g.h[vj];
+          if (fabs(v) > amax) amax = fabs(v);
+        }
+    } else {
+      int64_t nx = 1;
+      for (int m = 0; m < g.dx; ++m) nx *= (int64_t)g.cells[m];
+      for (int m = 0; m < g.dx; ++m) nx *= g.n;
+      for (int64_t t = 0; t < nx; ++t) {
+        double v = fabs(field->sign * field->E[t * g.dx + (j - g.dx)]);
+        if (v > amax) amax = v;
+      }
+    }
+    sum += amax / g.h[j];
+  }
+  if (!(sum > 0.0)) return -1.0;
+  return cfl / ((2.0 * k + 1.0) * sum);
+}
+
+int or_init_state(const or_mesh *mesh, int k, int kind, const double *params,
+                  double *u) {
+  or_geom g;
+  if (setup_geom(mesh, k, &g)) return -1;
+  if (kind != 0 && kind != 1) return -1;
+  const double alpha = (kind == 1 && params) ? params[0] : 0.0;
+#pragma omp parallel for schedule(static)
+  for (int64_t c = 0; c < g.ncells; ++c) {
+    int cm[OR_MAXD], qm[OR_MAXD];
+    cell_multi(&g, c, cm);
+    for (int64_t q = 0; q < g.nd; ++q) {
+      node_multi(&g, q, qm);
+      double v;
+      if (kind == 0) {
+        v = 1.0;
+        for (int j = 0; j < g.d; ++j) {
+          double x = node_coord(&g, cm, qm, j);
+          v *= sin(2.0 * OR_PI * (x - g.lo[j]) / (g.hi[j] - g.lo[j]));
+        }
+      } else {
+        double x1 = node_coord(&g, cm, qm, 0);
+        double v2 = 0.0;
+        for (int j = g.dx; j < g.d; ++j) {
+          double vj = node_coord(&g, cm, qm, j);
+          v2 += vj * vj;
+        }
+        v = (1.0 + alpha * cos(2.0 * OR_PI * (x1 - g.lo[0]) / (g.hi[0] - g.lo[0]))) *
+            pow(2.0 * OR_PI, -0.5 * g.dv) * exp(-0.5 * v2);
+      }
+      u[c * g.nd + q] = v;
+    }
+  }
+  return 0;
+}
+
+int or_field_sine_table(const or_mesh *mesh, int k, double amp, double *E) {
+  or_geom g;
+  if (setup_geom(mesh, k, &g)) return -1;
+  int64_t nxc = 1, nxn = 1;
+  for (int m = 0; m < g.dx; ++m) {
+    nxc *= g.cells[m];
+    nxn *= g.n;
+  }
+  for (int64_t xc = 0; xc < nxc; ++xc)
+    for (int64_t xn = 0; xn < nxn; ++xn) {
+      int64_t cr = xc, nr = xn;
+      for (int m = 0; m < g.dx; ++m) {
+        int cmm = (int)(cr % g.cells[m]);
+        int qmm = (int)(nr % g.n);
+        cr /= g.cells[m];
+        nr /= g.n;
+        double x = g.lo[m] + (cmm + g.xi[qmm]) * g.h[m];
+        E[(xc * nxn + xn) * g.dx + m] =
+            amp * sin(2.0 * OR_PI * (x - g.lo[m]) / (g.hi[m] - g.lo[m]));
+      }
+    }
+  return 0;
+}
+
+int or_diagnostics(const or_mesh *mesh, int k, const double *u, double *mass,
+                   double *energy) {
+  or_geom g;
+  if (setup_geom(mesh, k, &g)) return -1;
+  double ms = 0.0, en = 0.0;
+#pragma omp parallel for reduction(+ : ms, en) schedule(static)
+  for (int64_t c = 0; c < g.ncells; ++c) {
+    int qm[OR_MAXD];
+    for (int64_t q = 0; q < g.nd; ++q) {
+      node_multi(&g, q, qm);
+      double W = vol_weight(&g, qm);
+      double v = u[c * g.nd + q];
+      ms += W * v;
+      en += W * v * v;
+    }
+  }
+  *mass = ms;
+  *energy = en;
+  return 0;
+}
+
+int or_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

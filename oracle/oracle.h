@@ -1,0 +1,119 @@
+/*
+ * Plain CPU oracle for the upwind, Gauss-Lobatto-collocation DG advection
+ * operator on a periodic Cartesian box and its low-storage RK integrator.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product library links, includes
+ * or calls this code; it exists so that tests and the benchmark's CPU
+ * baseline can check the GPU path against a slow, obviously correct
+ * evaluation of the same discrete operator. It shares no source with the
+ * GPU library.
+ *
+ * Paper: Munch, Kormann, Kronbichler, "hyper.deal: An efficient, matrix-free
+ * finite-element library for high-dimensional partial differential
+ * equations" (arXiv 2002.08110).
+ *
+ *  - Model problem: conservative advection df/dt + div(a f) = 0 with periodic
+ *    boundaries (Sec. 1.2, eq. intro:advection); for phase space the field is
+ *    a = (v, E(x)) (Sec. 1.2, eq. intro:vp:simple; Sec. 6.1).
+ *  - DG weak form with a numerical flux (Sec. 1.3), nodal tensor-product
+ *    basis on Gauss-Lobatto points (Sec. 2.3), Gauss-Lobatto quadrature in
+ *    the same points (collocation, Sec. 2.5), diagonal mass matrix (Sec. 1.3).
+ *  - Element-centric evaluation of one cell with its 2d faces (Sec. 3.4,
+ *    Algorithms 1 and 2).
+ *  - Five-stage, fourth-order low-storage Runge-Kutta scheme with three
+ *    solution-sized vectors (Sec. 5.4).
+ *
+ * Every function is parity-pinned by the CPU tests (tests/test_oracle_*.py)
+ * against closed forms, invariants and exact solutions; none is "parity
+ * unpinned".
+ */
+#ifndef HD_ORACLE_H
+#define HD_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Periodic Cartesian box, dim_x configuration dims first, then dim_v
+ * velocity dims; cells[j] cells of width (hi[j]-lo[j])/cells[j] in dim j. */
+typedef struct {
+  int dim_x, dim_v;
+  int cells[6];
+  double lo[6], hi[6];
+} or_mesh;
+
+/* Advection field.
+ *  kind 0: constant a[0..d-1].
+ *  kind 1: phase space, a_{x_j} = v_j (the coordinate of velocity dim j) and
+ *          a_{v_j} = sign * E_j(x), with E given at the x-nodes:
+ *          E[((xcell * n^dx) + xnode) * dx + j], xcell lexicographic over the
+ *          x-cells (dim 1 fastest), xnode lexicographic over the x-node
+ *          indices (dim 1 fastest). Requires dim_x == dim_v. */
+typedef struct {
+  int kind;
+  double a[6];
+  const double *E;
+  double sign;
+} or_field;
+
+/* Gauss-Lobatto rule with k+1 points on [0,1]; xi ascending, sum w = 1.
+ * Returns 0, or -1 for k < 1 or k > 16. */
+int or_gl_rule(int k, double *xi, double *w);
+
+/* Lagrange polynomial l_m on the GL points of degree k, and its derivative. */
+double or_lagrange(int k, const double *xi, int m, double x);
+double or_lagrange_deriv(int k, const double *xi, int m, double x);
+
+/* Number of DoFs, n^d * prod(cells). */
+int64_t or_num_dofs(const or_mesh *mesh, int k);
+
+/* Node coordinates: X[dof * d + j] for the canonical DoF numbering
+ * (dof = cell * n^d + node, cell and node lexicographic, dim 1 fastest). */
+int or_node_coords(const or_mesh *mesh, int k, double *X);
+
+/* Evaluate out = M^{-1} A(u) for the listed cells (out holds n^d values per
+ * listed cell, in list order). mode 0: full basis (every phi_i evaluated at
+ * every quadrature point); mode 1: the same sums with structurally zero
+ * basis values skipped. Returns 0, or -1 on invalid input. */
+int or_apply_cells(const or_mesh *mesh, int k, const or_field *field, int mode,
+                   const double *u, const int64_t *cells, int64_t ncells,
+                   double *out);
+
+/* out = M^{-1} A(u) on all cells. */
+int or_apply(const or_mesh *mesh, int k, const or_field *field, int mode,
+             const double *u, double *out);
+
+/* The 2N-storage, five-stage, fourth-order RK coefficients (A, B, C). */
+void or_lsrk45_coefficients(double *A, double *B, double *C);
+
+/* nsteps steps of the low-storage RK scheme with time step dt, in place on u. */
+int or_rk_steps(const or_mesh *mesh, int k, const or_field *field, int mode,
+                double dt, int nsteps, double *u);
+
+/* dt = cfl / ((2k+1) * sum_j max|a_j| / h_j). */
+double or_stable_dt(const or_mesh *mesh, int k, const or_field *field,
+                    double cfl);
+
+/* Initial state by nodal interpolation.
+ *  kind 0: prod_j sin(2 pi (x_j - lo_j)/(hi_j - lo_j)).
+ *  kind 1: (1 + p[0] cos(2 pi (x_1 - lo_1)/(hi_1 - lo_1)))
+ *          * (2 pi)^(-dv/2) exp(-|v|^2 / 2). */
+int or_init_state(const or_mesh *mesh, int k, int kind, const double *params,
+                  double *u);
+
+/* E_j(x) = amp * sin(2 pi (x_j - lo_j)/(hi_j - lo_j)) tabulated at x-nodes. */
+int or_field_sine_table(const or_mesh *mesh, int k, double amp, double *E);
+
+/* mass = sum W_i u_i, energy = sum W_i u_i^2, W_i = prod_j h_j w_{i_j}. */
+int or_diagnostics(const or_mesh *mesh, int k, const double *u, double *mass,
+                   double *energy);
+
+/* Number of OpenMP threads the oracle uses. */
+int or_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
