@@ -1,0 +1,196 @@
+"""Benchmark of the fused DG advection RK stage on one MI355X.
+
+Workload: 6D phase-space advection (3 x + 3 v dims), 8^6 cells, degree 3
+(4096 DoFs per cell, 1,073,741,824 DoFs), a = (v, 0.1 sin(2 pi x)), the
+perturbed-Maxwellian initial state, LSRK45 with CFL 0.2. A "step" is one
+full RK step (5 fused stage launches) over the whole state, which is
+resident in HBM before timing starts. The metric is DoF updates per second
+per RK stage (N_DoF / t_stage, t_stage = t_step / 5); the headline value is
+FP64, the FP32-operator mode is reported beside it.
+
+Prints ONE JSON line (rank 0, N = 1).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0     # MI355X HBM3E peak
+PAPER_GDOFS_PER_NODE = 1.12  # 6D k=3 32^6 DoFs per SuperMUC-NG node, context only
+# Algorithmic bytes per DoF of the five fused stages: stage 1 reads u and
+# writes du and u'; stages 2-4 read u, du and write du, u'; stage 5 reads u,
+# du and writes u'. u is FP64, du has the operator precision.
+def stage_bytes(psize):
+    return [8 + psize + 8, 8 + 2 * psize + 8, 8 + 2 * psize + 8, 8 + 2 * psize + 8, 8 + psize + 8]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="6d", choices=["6d", "4d", "6d_small", "2d"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--precisions", default="fp64,fp32")
+    ap.add_argument("--plan", default="", help="override plan, e.g. lds=1,reg_dims=1")
+    return ap.parse_args()
+
+
+def measure(case, precision, steps, warmup, plan_override):
+    import torch
+
+    from paper_2002_08110_amd.solver import Solver
+    S = Solver(case.dim_x, case.dim_v, case.cells, case.lo, case.hi, case.degree,
+               precision=precision)
+    if case.field == "sine":
+        S.set_field_sine(case.amp)
+    else:
+        S.set_field_constant(case.a)
+    if plan_override:
+        S.set_plan(**plan_override)
+    S.init_state(case.ic, list(case.ic_params))
+    dt = S.stable_dt(case.cfl)
+    stream = torch.cuda.current_stream()
+    m0, e0 = S.diagnostics()
+    S.rk_step(dt, warmup)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    t0.record(stream)
+    S.rk_step(dt, steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_step = t0.elapsed_time(t1) / steps
+    # Per-stage kernel durations: each stage launch bracketed by events on
+    # the stream it runs on.
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    reps = max(2, min(steps, 5))
+    stage_ms = np.zeros(5)
+    for _ in range(reps):
+        for st in range(5):
+            evs[st].record(stream)
+            S.rk_stage(st, dt)
+        evs[5].record(stream)
+        torch.cuda.synchronize()
+        for st in range(5):
+            stage_ms[st] += evs[st].elapsed_time(evs[st + 1])
+    stage_ms /= reps
+    m1, e1 = S.diagnostics()
+    psize = 4 if precision == "fp32" else 8
+    byts = np.array(stage_bytes(psize), dtype=float) * S.ndofs
+    achieved = byts.sum() / (stage_ms.sum() * 1e-3) / 1e9
+    res = dict(
+        precision=precision, ndofs=S.ndofs, dt=dt, ms_per_step=ms_step, wall_s=wall,
+        dof_updates_per_s=S.ndofs * 5 / (ms_step * 1e-3),
+        stage_ms=[round(x, 4) for x in stage_ms],
+        stage_kernel_GBps=achieved, algorithmic_bytes_per_dof=float(np.mean(stage_bytes(psize))),
+        plan=S.get_plan(), mass_drift=(m1 - m0) / abs(m0), energy_ratio=e1 / e0,
+    )
+    S.close()
+    del S
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(case, seconds):
+    """The oracle (zero-skipping mode, OpenMP over cells) on a bounded sample
+    of cells of the same workload; throughput in DoF updates per second."""
+    import oracle
+    P = oracle.Problem(case.dim_x, case.dim_v, case.cells, case.lo, case.hi, case.degree,
+                       field="phase" if case.field == "sine" else "constant",
+                       sine_amp=case.amp if case.field == "sine" else None, a=case.a)
+    nd = P.n ** P.d
+    u = np.zeros(P.ndofs)  # pages the sample never touches stay unallocated
+    rng = np.random.default_rng(5)
+    ncells = P.ncells
+    # Calibrate on a few cells, then size the sample to about `seconds`.
+    sample = rng.choice(ncells, size=min(ncells, 64), replace=False).astype(np.int64)
+    t = time.perf_counter()
+    P.apply_cells(u, sample)
+    per_cell = (time.perf_counter() - t) / len(sample)
+    count = int(min(ncells, max(64, seconds / max(per_cell, 1e-9))))
+    sample = rng.choice(ncells, size=count, replace=False).astype(np.int64)
+    t = time.perf_counter()
+    P.apply_cells(u, sample)
+    el = time.perf_counter() - t
+    return {"value": count * nd / el, "unit": "DoF-updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "%d of %d cells of %s (operator evaluation per cell, zero-skipping mode), "
+                      "%.1f s" % (count, ncells, case.name, el)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2002_08110_amd import _hd
+    from paper_2002_08110_amd import workloads as W
+    if not os.path.exists(_hd.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    case = {"6d": W.CONFIG_6D, "4d": W.CONFIG_4D, "6d_small": W.CONFIG_6D_SMALL,
+            "2d": W.CONFIG_2D}[args.config]
+    plan = {}
+    if args.plan:
+        for kv in args.plan.split(","):
+            k, v = kv.split("=")
+            plan[k] = int(v)
+    results = {}
+    for prec in args.precisions.split(","):
+        results[prec] = measure(case, prec, args.steps, args.warmup, plan)
+        print("# %s: %.1f GDoF/s per stage, stage kernels %.0f GB/s, stages ms %s, plan %s"
+              % (prec, results[prec]["dof_updates_per_s"] / 1e9,
+                 results[prec]["stage_kernel_GBps"], results[prec]["stage_ms"],
+                 results[prec]["plan"]), file=sys.stderr, flush=True)
+    head = results.get("fp64") or next(iter(results.values()))
+    achieved = head["stage_kernel_GBps"]
+    line = {
+        "metric": "6D k=3 DoF-updates/s per RK stage, FP64 vs FP32, % HBM peak; p99 latency",
+        "value": head["dof_updates_per_s"],
+        "unit": "DoF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if head["precision"] == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": case.name, "cells": case.cells, "degree": case.degree,
+                   "ndofs": head["ndofs"], "field": "a=(v, 0.1 sin(2 pi x))",
+                   "initial_state": "(1+0.01 cos(2 pi x1)) Maxwellian(v)",
+                   "rk": "LSRK45 (5 fused stages per step)", "cfl": case.cfl},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "kernel": "stage_kernel (fused LSRK stage)",
+                     "algorithmic_bytes_per_dof": head["algorithmic_bytes_per_dof"]},
+        "pct_hbm_peak": 100.0 * achieved / HBM_PEAK_GBPS,
+        "modes": {p: {k: r[k] for k in ("dof_updates_per_s", "ms_per_step", "stage_ms",
+                                        "stage_kernel_GBps", "algorithmic_bytes_per_dof",
+                                        "plan", "mass_drift", "energy_ratio")}
+                  for p, r in results.items()},
+        "paper_context": {"value": PAPER_GDOFS_PER_NODE * 1e9, "unit": "DoF-updates/s",
+                          "hardware": "1 SuperMUC-NG node, 2x24-core Xeon 8174, FP64, "
+                                      "Gauss quadrature, deformed mesh"},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

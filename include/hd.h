@@ -1,0 +1,184 @@
+/*
+ * hd.h - C ABI of the MI355X (gfx950) library for the matrix-free,
+ * upwind, Gauss-Lobatto-collocation discontinuous Galerkin advection
+ * operator in 2 to 6 dimensions on a tensor product of a configuration-space
+ * mesh and a velocity-space mesh, advanced by a five-stage fourth-order
+ * low-storage Runge-Kutta scheme.
+ *
+ * Paper: Munch, Kormann, Kronbichler, "hyper.deal: An efficient,
+ * matrix-free finite-element library for high-dimensional partial
+ * differential equations", arXiv 2002.08110.
+ *
+ * General conventions (every function):
+ *  - Return value: hd_status; HD_OK (0) on success, a negative code on error.
+ *    The message of the last error on the calling thread is returned by
+ *    hd_last_error(). No C++ exception crosses this boundary.
+ *  - Streams: `hd_stream` is a hipStream_t passed as void*; NULL is the
+ *    default stream. Work is enqueued asynchronously on that stream unless a
+ *    function says it synchronizes.
+ *  - Ownership: an hd_solver belongs to the caller from hd_create until
+ *    hd_destroy. Device memory handed to hd_bind belongs to the caller and
+ *    must outlive the solver's use; the library never frees it. Host arrays
+ *    are only read (or written) during the call.
+ *  - Canonical DoF layout (the layout of every state vector crossing the
+ *    ABI): dof = cell * (k+1)^d + node. The cell index is lexicographic over
+ *    (c_1..c_d) with dimension 1 fastest, dimensions ordered x_1..x_dx then
+ *    v_1..v_dv (x-fastest cell enumeration, Sec. 3.2); the node index is
+ *    lexicographic over the Gauss-Lobatto node indices (i_1..i_d), dimension
+ *    1 fastest. Nodes lie at lo_j + (c_j + xi_{i_j}) h_j with xi the
+ *    Gauss-Lobatto points on [0,1] (Sec. 2.3).
+ *  - Errors: HD_ERR_INVALID for bad arguments (dim_x or dim_v outside 1..3,
+ *    degree < 1, a cell count < 1, lo >= hi, NULL pointers, a call that needs
+ *    bound memory before hd_bind, a buffer smaller than required);
+ *    HD_ERR_UNSUPPORTED for valid input with no compiled kernel (degree > 5);
+ *    HD_ERR_HIP when a HIP call fails (its message is kept).
+ */
+#ifndef HD_H
+#define HD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HD_OK = 0,
+  HD_ERR_INVALID = -1,
+  HD_ERR_UNSUPPORTED = -2,
+  HD_ERR_OOM = -3,
+  HD_ERR_HIP = -4,
+  HD_ERR_STATE = -5
+} hd_status;
+
+/* Operator precision. HD_FP64: operator, stage increment and solution in
+ * FP64. HD_FP32: operator and stage increment du in FP32 (FP32
+ * accumulation); the solution u stays FP64. */
+typedef enum { HD_FP64 = 0, HD_FP32 = 1 } hd_precision;
+
+/* Periodic Cartesian box: the tensor product of a dim_x-dimensional
+ * configuration mesh and a dim_v-dimensional velocity mesh (Sec. 3.1),
+ * x dims first. cells[j] cells of width (hi[j]-lo[j])/cells[j] in dim j;
+ * entries beyond dim_x + dim_v are ignored. */
+typedef struct {
+  int dim_x, dim_v;
+  int cells[6];
+  double lo[6], hi[6];
+} hd_mesh;
+
+typedef void *hd_stream;             /* hipStream_t */
+typedef struct hd_solver hd_solver;  /* opaque */
+typedef struct hd_batch hd_batch;    /* opaque */
+
+/* Launch plan of the fused stage kernel (chosen by the autotuner).
+ *  lds:        1 = stage each cell's values in LDS for the sweeps along
+ *              thread-distributed dimensions; 0 = read them from global memory.
+ *  cells_per_wg: cells per workgroup (lds = 1) - ignored for lds = 0.
+ *  wg_size:    threads per workgroup for lds = 0 (multiple of 64, <= 1024).
+ *  xcd_remap:  1 = map consecutive cell tiles to the same XCD.
+ *  reg_dims:   number of slowest dimensions whose lines a thread keeps in
+ *              registers (1 or 2; at most dim_v). */
+typedef struct {
+  int lds;
+  int cells_per_wg;
+  int wg_size;
+  int xcd_remap;
+  int reg_dims;
+} hd_plan;
+
+/* Create a solver for `mesh` and polynomial degree `degree` (k+1 nodes per
+ * dimension; degree 1..5 compiled) with precision `prec` (hd_precision).
+ * The field defaults to constant zero. Allocates no device memory. */
+hd_status hd_create(const hd_mesh *mesh, int degree, int prec, hd_solver **out);
+
+/* Destroy a solver (the caller's bound memory is not freed). NULL is a no-op. */
+hd_status hd_destroy(hd_solver *s);
+
+/* Number of DoFs N = |C| (k+1)^d (Sec. 2.3, eq. dealii:totalunkonwns). */
+hd_status hd_num_dofs(const hd_solver *s, int64_t *ndofs);
+
+/* Bytes of device workspace the solver needs: two FP64 solution vectors
+ * (input and output of a stage), the stage increment du (FP64 or FP32),
+ * the field table and reduction scratch, each 256-byte aligned. */
+hd_status hd_required_bytes(const hd_solver *s, size_t *workspace_bytes);
+
+/* Hand the solver caller-owned device memory of at least
+ * hd_required_bytes(); the solution starts as zero after hd_bind. */
+hd_status hd_bind(hd_solver *s, void *workspace_dev, size_t bytes);
+
+/* Constant advection field a (d entries) - the field of the paper's
+ * performance runs (Sec. 5.1). Synchronous. */
+hd_status hd_set_field_constant(hd_solver *s, const double *a);
+
+/* Phase-space field a = (v, sign * E(x)) (Sec. 1.2 eq. intro:vp:simple,
+ * Sec. 6.1): a_{x_j} is the velocity coordinate v_j, a_{v_j} = sign*E_j(x).
+ * E_host holds E at the configuration-space nodes,
+ * E[((xcell * (k+1)^dx) + xnode) * dx + j], xcell and xnode lexicographic
+ * (dim 1 fastest). Requires dim_x == dim_v. Copied to device; synchronous.
+ * Requires hd_bind. */
+hd_status hd_set_field_phase_space(hd_solver *s, const double *E_host, double sign);
+
+/* Phase-space field with E_j(x) = amp * sin(2 pi (x_j - lo_j)/(hi_j - lo_j))
+ * at the configuration nodes. Requires hd_bind. Synchronous. */
+hd_status hd_set_field_sine(hd_solver *s, double amp, double sign);
+
+/* Copy a canonical FP64 state (host or device pointer) into the solution. */
+hd_status hd_set_state(hd_solver *s, const double *u, int u_is_device, hd_stream stream);
+
+/* Nodal interpolation of an initial state on the device.
+ *  kind 0: prod_j sin(2 pi (x_j - lo_j)/(hi_j - lo_j));
+ *  kind 1: (1 + params[0] cos(2 pi (x_1 - lo_1)/(hi_1 - lo_1)))
+ *          * (2 pi)^(-dv/2) exp(-|v|^2/2). */
+hd_status hd_init_state(hd_solver *s, int kind, const double *params, hd_stream stream);
+
+/* Device pointer to the current FP64 solution (N doubles, canonical). It
+ * moves between the two solution buffers after each RK stage. */
+hd_status hd_state_ptr(const hd_solver *s, void **dev_ptr);
+
+/* Copy the current solution to host memory (N doubles). Synchronizes. */
+hd_status hd_get_state(const hd_solver *s, double *u_host, hd_stream stream);
+
+/* out = M^{-1} A(in): the element-centric evaluation of Algorithm 2 (cell
+ * integral, 2d upwind face integrals, diagonal inverse mass) on every cell.
+ * in: N FP64 values on the device (canonical, must not alias out);
+ * out: N values on the device, FP64 for HD_FP64 and FP32 for HD_FP32. */
+hd_status hd_apply(hd_solver *s, const double *in_dev, void *out_dev, hd_stream stream);
+
+/* dt = cfl / ((2k+1) sum_j max|a_j| / h_j) for the current field. */
+hd_status hd_stable_dt(const hd_solver *s, double cfl, double *dt);
+
+/* One stage (stage = 0..4) of the low-storage RK scheme (Sec. 5.4), fused
+ * into one pass: du <- A_s du + dt M^{-1}A(u); u <- u + B_s du. */
+hd_status hd_rk_stage(hd_solver *s, int stage, double dt, hd_stream stream);
+
+/* nsteps full RK steps (5 fused stages each), replayed from a hipGraph
+ * captured per (dt, solution buffer parity). */
+hd_status hd_rk_step(hd_solver *s, double dt, int nsteps, hd_stream stream);
+
+/* mass = sum_i W_i u_i, energy = sum_i W_i u_i^2 with W_i = prod_j h_j w_{i_j},
+ * in FP64 with a fixed reduction order (bitwise reproducible). Synchronizes. */
+hd_status hd_diagnostics(const hd_solver *s, double *mass, double *energy, hd_stream stream);
+
+/* Read / override the stage-kernel launch plan. */
+hd_status hd_get_plan(const hd_solver *s, hd_plan *plan);
+hd_status hd_set_plan(hd_solver *s, const hd_plan *plan);
+
+/* Message of the last error on this thread ("" if none). */
+const char *hd_last_error(void);
+
+/* Several bound solvers advanced together: each RK stage of every active
+ * solve runs in one persistent launch over a shared work list, and a whole
+ * step (5 launches) is replayed from one hipGraph. The solvers stay owned
+ * by the caller and must outlive the batch. */
+hd_status hd_batch_create(hd_solver *const *solvers, int n, hd_batch **out);
+hd_status hd_batch_destroy(hd_batch *b);
+
+/* One RK step of every solver i with active[i] != 0 (active may be NULL =
+ * all), with time step dt[i]. */
+hd_status hd_batch_step(hd_batch *b, const double *dt, const int *active, hd_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HD_H */

@@ -1,0 +1,722 @@
+// C ABI of the library (declared in include/hd.h): solver objects, argument
+// checking, workspace layout, field tables, initial states, the fused RK
+// stage launches, hipGraph capture of whole RK steps, deterministic FP64
+// diagnostics and the batched persistent-launch path.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gl_tables.h"
+#include "hd.h"
+#include "stage_dispatch.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+hd_status fail(hd_status st, const std::string &msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HD_HIP(expr)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(HD_ERR_HIP, std::string(#expr) + " failed: " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int kDiagBlocks = 1024;
+constexpr int kDiagThreads = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Carpenter & Kennedy (1994) five-stage fourth-order 2N-storage scheme,
+// the low-storage RK scheme of Sec. 5.4 (order 4, 5 stages, 3 vectors).
+const double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0,
+                        -2404267990393.0 / 2016746695238.0,
+                        -3550918686646.0 / 2091501179385.0,
+                        -1275806237668.0 / 842570457699.0};
+const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                        1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                        2277821191437.0 / 14882151754819.0};
+
+}  // namespace
+
+struct hd_solver {
+  hd_mesh mesh{};
+  int d = 0, dx = 0, dv = 0, k = 0, n = 0, prec = 0;
+  int64_t nd = 0, ncells = 0, ndofs = 0;
+  double h[6] = {0};
+  hd::Tables1D tab;
+  int field_kind = 0;
+  double a_const[6] = {0};
+  double esign = 1.0;
+  std::vector<double> E_host;  // E at x-nodes (phase-space field)
+  int64_t nE = 0;              // entries of the E table
+  // Workspace layout (offsets into the caller's buffer).
+  size_t off_u[2] = {0, 0}, off_du = 0, off_E = 0, off_part = 0, total = 0;
+  char *ws = nullptr;
+  int cur = 0;  // which of the two solution buffers holds the solution
+  hd_plan plan{};
+  // Captured RK steps (index = solution buffer parity at the start).
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  double gdt = 0.0;
+  bool gvalid = false;
+
+  double *u(int i) const { return reinterpret_cast<double *>(ws + off_u[i]); }
+  void *du() const { return ws + off_du; }
+  void *E() const { return ws + off_E; }
+  double *part() const { return reinterpret_cast<double *>(ws + off_part); }
+  size_t psize() const { return prec == HD_FP32 ? sizeof(float) : sizeof(double); }
+};
+
+
+namespace {
+
+bool valid_plan(const hd_solver *s, const hd_plan &p, std::string *why) {
+  const int rd = p.reg_dims;
+  if (rd < 1 || rd > 2 || rd > s->dv) {
+    *why = "reg_dims must be 1 or 2 and at most dim_v";
+    return false;
+  }
+  int64_t T = 1;
+  for (int j = 0; j < s->d - rd; ++j) T *= s->n;
+  if (p.lds) {
+    const int64_t cell_bytes = s->nd * (int64_t)s->psize();
+    if (T > 1024 || p.cells_per_wg < 1 || p.cells_per_wg * T > 1024 ||
+        p.cells_per_wg * cell_bytes > (int64_t)hd::kMaxLdsBytes) {
+      *why = "LDS plan does not fit (threads <= 1024, LDS <= 160 KiB per workgroup)";
+      return false;
+    }
+    if (T > 256 && p.cells_per_wg != 1) {
+      *why = "cells with more than 256 pencils take one cell per workgroup";
+      return false;
+    }
+    if (T <= 256 && p.cells_per_wg * T > 256) {
+      *why = "workgroups of cells with <= 256 pencils hold at most 256 threads";
+      return false;
+    }
+  } else {
+    if (p.wg_size < 64 || p.wg_size > 256 || p.wg_size % 64) {
+      *why = "wg_size must be 64, 128, 192 or 256";
+      return false;
+    }
+  }
+  return true;
+}
+
+hd_plan default_plan(const hd_solver *s) {
+  hd_plan p{};
+  p.xcd_remap = 1;
+  p.wg_size = 256;
+  p.reg_dims = (s->n <= 3 && s->dv >= 2) ? 2 : 1;
+  int64_t T = 1;
+  for (int j = 0; j < s->d - p.reg_dims; ++j) T *= s->n;
+  const int64_t cell_bytes = s->nd * (int64_t)s->psize();
+  if (T <= 1024 && cell_bytes <= (int64_t)hd::kMaxLdsBytes) {
+    p.lds = 1;
+    int cpw = T <= 256 ? (int)(256 / T) : 1;
+    while (cpw > 1 && cpw * cell_bytes > (int64_t)hd::kMaxLdsBytes) --cpw;
+    p.cells_per_wg = std::max(1, cpw);
+  } else {
+    p.lds = 0;
+    p.cells_per_wg = 1;
+  }
+  return p;
+}
+
+template <typename P>
+void fill_params(const hd_solver *s, hd::StageParams<P> *prm) {
+  std::memset(prm, 0, sizeof(*prm));
+  prm->ncells = (unsigned)s->ncells;
+  unsigned st = 1;
+  for (int j = 0; j < s->d; ++j) {
+    prm->cells[j] = (unsigned)s->mesh.cells[j];
+    prm->cstride[j] = st;
+    st *= (unsigned)s->mesh.cells[j];
+    prm->inv_h[j] = (P)(1.0 / s->h[j]);
+    // lift = 1 / w_0 = 1 / w_k (boundary Gauss-Lobatto weight on [0,1]).
+    prm->lift_inv_h[j] = (P)(1.0 / (s->tab.w[0] * s->h[j]));
+    prm->a_const[j] = (P)s->a_const[j];
+    prm->vlo[j] = (P)s->mesh.lo[j];
+    prm->vh[j] = (P)s->h[j];
+  }
+  for (int m = 0; m < s->n; ++m) prm->xi[m] = (P)s->tab.xi[m];
+  for (int q = 0; q < s->n * s->n; ++q) prm->Dm[q] = (P)s->tab.D[q];
+  prm->field_kind = s->field_kind;
+  prm->esign = (P)s->esign;
+  prm->E = reinterpret_cast<const P *>(s->E());
+  prm->xcd_remap = s->plan.xcd_remap;
+  prm->cells_per_wg = (unsigned)s->plan.cells_per_wg;
+}
+
+hd::LaunchShape shape_of(const hd_solver *s) {
+  hd::LaunchShape ls{};
+  int64_t T = 1;
+  for (int j = 0; j < s->d - s->plan.reg_dims; ++j) T *= s->n;
+  if (s->plan.lds) {
+    const int64_t cpw = s->plan.cells_per_wg;
+    ls.grid = (unsigned)((s->ncells + cpw - 1) / cpw);
+    ls.block = (unsigned)(cpw * T);
+    ls.shmem = (size_t)(cpw * s->nd) * s->psize();
+  } else {
+    const int64_t total = s->ncells * T;
+    ls.grid = (unsigned)((total + s->plan.wg_size - 1) / s->plan.wg_size);
+    ls.block = (unsigned)s->plan.wg_size;
+    ls.shmem = 0;
+  }
+  return ls;
+}
+
+template <typename P>
+hipError_t dispatch(const hd_solver *s, const hd::StageParams<P> &prm, const hd::LaunchShape &ls,
+                    hipStream_t st);
+
+template <>
+hipError_t dispatch<double>(const hd_solver *s, const hd::StageParams<double> &prm,
+                            const hd::LaunchShape &ls, hipStream_t st) {
+  const int rd = s->plan.reg_dims, lds = s->plan.lds, n = s->n;
+  switch (s->d) {
+    case 2: return hd::stage_d2_f64(n, rd, lds, prm, ls, st);
+    case 3: return hd::stage_d3_f64(n, rd, lds, prm, ls, st);
+    case 4: return hd::stage_d4_f64(n, rd, lds, prm, ls, st);
+    case 5: return hd::stage_d5_f64(n, rd, lds, prm, ls, st);
+    case 6: return hd::stage_d6_f64(n, rd, lds, prm, ls, st);
+  }
+  return hipErrorInvalidConfiguration;
+}
+
+template <>
+hipError_t dispatch<float>(const hd_solver *s, const hd::StageParams<float> &prm,
+                           const hd::LaunchShape &ls, hipStream_t st) {
+  const int rd = s->plan.reg_dims, lds = s->plan.lds, n = s->n;
+  switch (s->d) {
+    case 2: return hd::stage_d2_f32(n, rd, lds, prm, ls, st);
+    case 3: return hd::stage_d3_f32(n, rd, lds, prm, ls, st);
+    case 4: return hd::stage_d4_f32(n, rd, lds, prm, ls, st);
+    case 5: return hd::stage_d5_f32(n, rd, lds, prm, ls, st);
+    case 6: return hd::stage_d6_f32(n, rd, lds, prm, ls, st);
+  }
+  return hipErrorInvalidConfiguration;
+}
+
+// Supported field/mesh combinations for the split x/v dimensions: the d = 2..6
+// splits 1+1, 2+1, 2+2, 3+2, 3+3 are compiled.
+bool split_compiled(int dx, int dv) {
+  return (dx == 1 && dv == 1) || (dx == 2 && dv == 1) || (dx == 2 && dv == 2) ||
+         (dx == 3 && dv == 2) || (dx == 3 && dv == 3);
+}
+
+template <typename P>
+hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, int mode,
+                    int stage, double dt, hipStream_t st) {
+  hd::StageParams<P> prm;
+  fill_params<P>(s, &prm);
+  const hd::LaunchShape ls = shape_of(s);
+  prm.nblocks = ls.grid;
+  prm.u_in = in;
+  prm.mode = mode;
+  if (mode == 0) {
+    prm.out = reinterpret_cast<P *>(out);
+  } else {
+    prm.u_out = u_out;
+    prm.du = reinterpret_cast<P *>(s->du());
+    prm.read_du = stage > 0;    // A_1 = 0: the first stage needs no du
+    prm.write_du = stage < 4;   // du is dead after the last stage
+    prm.rk_a = (P)kRkA[stage];
+    prm.rk_b = kRkB[stage];
+    prm.dt = (P)dt;
+  }
+  if (ls.grid == 0) return HD_OK;
+  hipError_t e = dispatch<P>(s, prm, ls, st);
+  if (e != hipSuccess) return fail(HD_ERR_HIP, std::string("stage kernel launch: ") + hipGetErrorString(e));
+  return HD_OK;
+}
+
+hd_status enqueue_stage(hd_solver *s, int stage, double dt, hipStream_t st) {
+  const double *in = s->u(s->cur);
+  double *out = s->u(1 - s->cur);
+  hd_status r = s->prec == HD_FP32 ? launch_op<float>(s, in, nullptr, out, 1, stage, dt, st)
+                                   : launch_op<double>(s, in, nullptr, out, 1, stage, dt, st);
+  if (r == HD_OK) s->cur = 1 - s->cur;
+  return r;
+}
+
+void drop_graphs(hd_solver *s) {
+  for (int i = 0; i < 2; ++i)
+    if (s->gexec[i]) {
+      hipGraphExecDestroy(s->gexec[i]);
+      s->gexec[i] = nullptr;
+    }
+  s->gvalid = false;
+}
+
+hd_status check_bound(const hd_solver *s) {
+  if (!s) return fail(HD_ERR_INVALID, "solver is NULL");
+  if (!s->ws) return fail(HD_ERR_INVALID, "solver has no bound workspace (call hd_bind)");
+  return HD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Initial state (nodal interpolation) and diagnostics kernels.
+// ---------------------------------------------------------------------------
+
+struct GeomArgs {
+  int d, dx, n;
+  unsigned cells[6];
+  double lo[6], hi[6], h[6];
+  double xi[8], w[8];
+  long long nd, ndofs;
+};
+
+__global__ void init_kernel(GeomArgs g, int kind, double alpha, double *u) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.ndofs) return;
+  long long cell = i / g.nd, node = i - cell * g.nd;
+  double x[6];
+  for (int j = 0; j < g.d; ++j) {
+    const int c = (int)(cell % g.cells[j]);
+    cell /= g.cells[j];
+    const int q = (int)(node % g.n);
+    node /= g.n;
+    x[j] = g.lo[j] + (c + g.xi[q]) * g.h[j];
+  }
+  const double two_pi = 6.283185307179586476925286766559;
+  double v;
+  if (kind == 0) {
+    v = 1.0;
+    for (int j = 0; j < g.d; ++j) v *= sin(two_pi * (x[j] - g.lo[j]) / (g.hi[j] - g.lo[j]));
+  } else {
+    double v2 = 0.0;
+    for (int j = g.dx; j < g.d; ++j) v2 += x[j] * x[j];
+    const int dv = g.d - g.dx;
+    v = (1.0 + alpha * cos(two_pi * (x[0] - g.lo[0]) / (g.hi[0] - g.lo[0]))) *
+        pow(two_pi, -0.5 * dv) * exp(-0.5 * v2);
+  }
+  u[i] = v;
+}
+
+// Pass 1: block b reduces the contiguous chunk [b*chunk, (b+1)*chunk) in a
+// fixed order (strided per thread, then a fixed tree), so the result is
+// bitwise reproducible.
+__global__ void __launch_bounds__(kDiagThreads) diag_kernel1(GeomArgs g, const double *u, long long chunk, double *part) {
+  __shared__ double sm[2][kDiagThreads];
+  const long long b0 = (long long)blockIdx.x * chunk;
+  const long long b1 = min(b0 + chunk, g.ndofs);
+  double m = 0.0, e = 0.0;
+  for (long long i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
+    long long node = i % g.nd;
+    double W = 1.0;
+    for (int j = 0; j < g.d; ++j) {
+      W *= g.h[j] * g.w[node % g.n];
+      node /= g.n;
+    }
+    const double v = u[i];
+    m += W * v;
+    e += W * v * v;
+  }
+  sm[0][threadIdx.x] = m;
+  sm[1][threadIdx.x] = e;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sm[0][threadIdx.x] += sm[0][threadIdx.x + s];
+      sm[1][threadIdx.x] += sm[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sm[0][0];
+    part[2 * blockIdx.x + 1] = sm[1][0];
+  }
+}
+
+__global__ void __launch_bounds__(kDiagThreads) diag_kernel2(const double *part, int nparts, double *res) {
+  __shared__ double sm[2][kDiagThreads];
+  double m = 0.0, e = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+    m += part[2 * i];
+    e += part[2 * i + 1];
+  }
+  sm[0][threadIdx.x] = m;
+  sm[1][threadIdx.x] = e;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sm[0][threadIdx.x] += sm[0][threadIdx.x + s];
+      sm[1][threadIdx.x] += sm[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    res[0] = sm[0][0];
+    res[1] = sm[1][0];
+  }
+}
+
+GeomArgs geom_of(const hd_solver *s) {
+  GeomArgs g{};
+  g.d = s->d;
+  g.dx = s->dx;
+  g.n = s->n;
+  for (int j = 0; j < s->d; ++j) {
+    g.cells[j] = (unsigned)s->mesh.cells[j];
+    g.lo[j] = s->mesh.lo[j];
+    g.hi[j] = s->mesh.hi[j];
+    g.h[j] = s->h[j];
+  }
+  for (int m = 0; m < s->n; ++m) {
+    g.xi[m] = s->tab.xi[m];
+    g.w[m] = s->tab.w[m];
+  }
+  g.nd = s->nd;
+  g.ndofs = s->ndofs;
+  return g;
+}
+
+hd_status upload_E(hd_solver *s) {
+  const size_t n = (size_t)s->nE;
+  if (s->prec == HD_FP32) {
+    std::vector<float> tmp(s->E_host.begin(), s->E_host.end());
+    HD_HIP(hipMemcpy(s->E(), tmp.data(), n * sizeof(float), hipMemcpyHostToDevice));
+  } else {
+    HD_HIP(hipMemcpy(s->E(), s->E_host.data(), n * sizeof(double), hipMemcpyHostToDevice));
+  }
+  drop_graphs(s);
+  return HD_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// ABI
+// ===========================================================================
+
+extern "C" {
+
+const char *hd_last_error(void) { return g_err.c_str(); }
+
+hd_status hd_create(const hd_mesh *mesh, int degree, int prec, hd_solver **out) {
+  if (!mesh || !out) return fail(HD_ERR_INVALID, "NULL argument");
+  *out = nullptr;
+  if (mesh->dim_x < 1 || mesh->dim_x > 3 || mesh->dim_v < 1 || mesh->dim_v > 3)
+    return fail(HD_ERR_INVALID, "dim_x and dim_v must be in 1..3");
+  if (degree < 1) return fail(HD_ERR_INVALID, "degree must be >= 1");
+  if (prec != HD_FP64 && prec != HD_FP32) return fail(HD_ERR_INVALID, "unknown precision");
+  const int d = mesh->dim_x + mesh->dim_v;
+  long double cells_total = 1.0L;
+  for (int j = 0; j < d; ++j) {
+    if (mesh->cells[j] < 1) return fail(HD_ERR_INVALID, "cell counts must be >= 1");
+    if (!(mesh->hi[j] > mesh->lo[j]) || !std::isfinite(mesh->lo[j]) || !std::isfinite(mesh->hi[j]))
+      return fail(HD_ERR_INVALID, "need finite lo < hi in every dimension");
+    cells_total *= mesh->cells[j];
+  }
+  if (degree > 5) return fail(HD_ERR_UNSUPPORTED, "degrees 1..5 are compiled");
+  if (!split_compiled(mesh->dim_x, mesh->dim_v))
+    return fail(HD_ERR_UNSUPPORTED,
+                "compiled x+v splits are 1+1, 2+1, 2+2, 3+2, 3+3 (dim_x >= dim_v)");
+  if (cells_total >= 4294967296.0L) return fail(HD_ERR_INVALID, "more than 2^32-1 cells");
+  hd_solver *s = new (std::nothrow) hd_solver();
+  if (!s) return fail(HD_ERR_OOM, "host allocation failed");
+  s->mesh = *mesh;
+  s->dx = mesh->dim_x;
+  s->dv = mesh->dim_v;
+  s->d = d;
+  s->k = degree;
+  s->n = degree + 1;
+  s->prec = prec;
+  s->nd = 1;
+  s->ncells = 1;
+  for (int j = 0; j < d; ++j) {
+    s->nd *= s->n;
+    s->ncells *= mesh->cells[j];
+    s->h[j] = (mesh->hi[j] - mesh->lo[j]) / mesh->cells[j];
+  }
+  s->ndofs = s->nd * s->ncells;
+  if (!hd::make_tables(degree, &s->tab)) {
+    delete s;
+    return fail(HD_ERR_INVALID, "Gauss-Lobatto table construction failed");
+  }
+  int64_t nxc = 1, nxn = 1;
+  for (int j = 0; j < s->dx; ++j) {
+    nxc *= mesh->cells[j];
+    nxn *= s->n;
+  }
+  s->nE = nxc * nxn * s->dx;
+  const size_t N = (size_t)s->ndofs;
+  size_t off = 0;
+  s->off_u[0] = off;
+  off = align_up(off + N * sizeof(double));
+  s->off_u[1] = off;
+  off = align_up(off + N * sizeof(double));
+  s->off_du = off;
+  off = align_up(off + N * s->psize());
+  s->off_E = off;
+  off = align_up(off + (size_t)s->nE * s->psize());
+  s->off_part = off;
+  off = align_up(off + sizeof(double) * (2 * kDiagBlocks + 2));
+  s->total = off;
+  s->plan = default_plan(s);
+  *out = s;
+  return HD_OK;
+}
+
+hd_status hd_destroy(hd_solver *s) {
+  if (!s) return HD_OK;
+  drop_graphs(s);
+  if (s->cap) hipStreamDestroy(s->cap);
+  delete s;
+  return HD_OK;
+}
+
+hd_status hd_num_dofs(const hd_solver *s, int64_t *ndofs) {
+  if (!s || !ndofs) return fail(HD_ERR_INVALID, "NULL argument");
+  *ndofs = s->ndofs;
+  return HD_OK;
+}
+
+hd_status hd_required_bytes(const hd_solver *s, size_t *bytes) {
+  if (!s || !bytes) return fail(HD_ERR_INVALID, "NULL argument");
+  *bytes = s->total;
+  return HD_OK;
+}
+
+hd_status hd_bind(hd_solver *s, void *ws, size_t bytes) {
+  if (!s || !ws) return fail(HD_ERR_INVALID, "NULL argument");
+  if (bytes < s->total) return fail(HD_ERR_INVALID, "workspace smaller than hd_required_bytes");
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign)
+    return fail(HD_ERR_INVALID, "workspace must be 256-byte aligned");
+  drop_graphs(s);
+  s->ws = reinterpret_cast<char *>(ws);
+  s->cur = 0;
+  HD_HIP(hipMemset(s->ws, 0, s->total));
+  if (s->field_kind == 1) return upload_E(s);
+  return HD_OK;
+}
+
+hd_status hd_set_field_constant(hd_solver *s, const double *a) {
+  if (!s || !a) return fail(HD_ERR_INVALID, "NULL argument");
+  for (int j = 0; j < s->d; ++j)
+    if (!std::isfinite(a[j])) return fail(HD_ERR_INVALID, "field must be finite");
+  s->field_kind = 0;
+  for (int j = 0; j < 6; ++j) s->a_const[j] = j < s->d ? a[j] : 0.0;
+  drop_graphs(s);
+  return HD_OK;
+}
+
+hd_status hd_set_field_phase_space(hd_solver *s, const double *E_host, double sign) {
+  if (!s || !E_host) return fail(HD_ERR_INVALID, "NULL argument");
+  if (s->dx != s->dv) return fail(HD_ERR_INVALID, "phase-space field needs dim_x == dim_v");
+  hd_status r = check_bound(s);
+  if (r) return r;
+  s->E_host.assign(E_host, E_host + s->nE);
+  for (double v : s->E_host)
+    if (!std::isfinite(v)) return fail(HD_ERR_INVALID, "E must be finite");
+  s->field_kind = 1;
+  s->esign = sign;
+  return upload_E(s);
+}
+
+hd_status hd_set_field_sine(hd_solver *s, double amp, double sign) {
+  if (!s) return fail(HD_ERR_INVALID, "NULL argument");
+  if (s->dx != s->dv) return fail(HD_ERR_INVALID, "phase-space field needs dim_x == dim_v");
+  std::vector<double> E((size_t)s->nE);
+  int64_t nxc = 1, nxn = 1;
+  for (int j = 0; j < s->dx; ++j) {
+    nxc *= s->mesh.cells[j];
+    nxn *= s->n;
+  }
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int64_t xc = 0; xc < nxc; ++xc)
+    for (int64_t xn = 0; xn < nxn; ++xn) {
+      int64_t cr = xc, nr = xn;
+      for (int j = 0; j < s->dx; ++j) {
+        const int c = (int)(cr % s->mesh.cells[j]);
+        const int q = (int)(nr % s->n);
+        cr /= s->mesh.cells[j];
+        nr /= s->n;
+        const double x = s->mesh.lo[j] + (c + s->tab.xi[q]) * s->h[j];
+        E[(size_t)((xc * nxn + xn) * s->dx + j)] =
+            amp * std::sin(two_pi * (x - s->mesh.lo[j]) / (s->mesh.hi[j] - s->mesh.lo[j]));
+      }
+    }
+  return hd_set_field_phase_space(s, E.data(), sign);
+}
+
+hd_status hd_set_state(hd_solver *s, const double *u, int u_is_device, hd_stream stream) {
+  hd_status r = check_bound(s);
+  if (r) return r;
+  if (!u) return fail(HD_ERR_INVALID, "NULL state");
+  HD_HIP(hipMemcpyAsync(s->u(s->cur), u, sizeof(double) * (size_t)s->ndofs,
+                        u_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                        (hipStream_t)stream));
+  return HD_OK;
+}
+
+hd_status hd_init_state(hd_solver *s, int kind, const double *params, hd_stream stream) {
+  hd_status r = check_bound(s);
+  if (r) return r;
+  if (kind != 0 && kind != 1) return fail(HD_ERR_INVALID, "initial state kind must be 0 or 1");
+  const double alpha = (kind == 1 && params) ? params[0] : 0.0;
+  const GeomArgs g = geom_of(s);
+  const unsigned blocks = (unsigned)((s->ndofs + 255) / 256);
+  hipLaunchKernelGGL(init_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, g, kind, alpha,
+                     s->u(s->cur));
+  HD_HIP(hipGetLastError());
+  return HD_OK;
+}
+
+hd_status hd_state_ptr(const hd_solver *s, void **ptr) {
+  hd_status r = check_bound(s);
+  if (r) return r;
+  if (!ptr) return fail(HD_ERR_INVALID, "NULL argument");
+  *ptr = s->u(s->cur);
+  return HD_OK;
+}
+
+hd_status hd_get_state(const hd_solver *s, double *u_host, hd_stream stream) {
+  hd_status r = check_bound(s);
+  if (r) return r;
+  if (!u_host) return fail(HD_ERR_INVALID, "NULL argument");
+  HD_HIP(hipMemcpyAsync(u_host, s->u(s->cur), sizeof(double) * (size_t)s->ndofs,
+                        hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HD_HIP(hipStreamSynchronize((hipStream_t)stream));
+  return HD_OK;
+}
+
+hd_status hd_apply(hd_solver *s, const double *in, void *out, hd_stream stream) {
+  hd_status r = check_bound(s);
+  if (r) return r;
+  if (!in || !out) return fail(HD_ERR_INVALID, "NULL argument");
+  const char *ib = reinterpret_cast<const char *>(in);
+  const char *ob = reinterpret_cast<const char *>(out);
+  const size_t ibytes = sizeof(double) * (size_t)s->ndofs, obytes = s->psize() * (size_t)s->ndofs;
+  if (ib < ob + obytes && ob < ib + ibytes) return fail(HD_ERR_INVALID, "in and out must not overlap");
+  return s->prec == HD_FP32 ? launch_op<float>(s, in, out, nullptr, 0, 0, 0.0, (hipStream_t)stream)
+                            : launch_op<double>(s, in, out, nullptr, 0, 0, 0.0, (hipStream_t)stream);
+}
+
+hd_status hd_stable_dt(const hd_solver *s, double cfl, double *dt) {
+  if (!s || !dt) return fail(HD_ERR_INVALID, "NULL argument");
+  if (!(cfl > 0)) return fail(HD_ERR_INVALID, "cfl must be > 0");
+  double sum = 0.0;
+  for (int j = 0; j < s->d; ++j) {
+    double amax = 0.0;
+    if (s->field_kind == 0) {
+      amax = std::fabs(s->a_const[j]);
+    } else if (j < s->dx) {
+      const int m = s->dx + j;
+      for (int c = 0; c < s->mesh.cells[m]; ++c)
+        for (int q = 0; q < s->n; ++q)
+          amax = std::max(amax, std::fabs(s->mesh.lo[m] + (c + s->tab.xi[q]) * s->h[m]));
+    } else {
+      for (int64_t t = j - s->dx; t < s->nE; t += s->dx)
+        amax = std::max(amax, std::fabs(s->esign * s->E_host[(size_t)t]));
+    }
+    sum += amax / s->h[j];
+  }
+  if (!(sum > 0)) return fail(HD_ERR_INVALID, "field is zero: no CFL time step");
+  *dt = cfl / ((2.0 * s->k + 1.0) * sum);
+  return HD_OK;
+}
+
+hd_status hd_rk_stage(hd_solver *s, int stage, double dt, hd_stream stream) {
+  hd_status r = check_bound(s);
+  if (r) return r;
+  if (stage < 0 || stage > 4) return fail(HD_ERR_INVALID, "stage must be 0..4");
+  if (!std::isfinite(dt)) return fail(HD_ERR_INVALID, "dt must be finite");
+  return enqueue_stage(s, stage, dt, (hipStream_t)stream);
+}
+
+hd_status hd_rk_step(hd_solver *s, double dt, int nsteps, hd_stream stream) {
+  hd_status r = check_bound(s);
+  if (r) return r;
+  if (nsteps < 0 || !std::isfinite(dt)) return fail(HD_ERR_INVALID, "need nsteps >= 0, finite dt");
+  if (nsteps == 0) return HD_OK;
+  if (!s->gvalid || s->gdt != dt) {
+    drop_graphs(s);
+    if (!s->cap) HD_HIP(hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking));
+    const int cur0 = s->cur;
+    for (int par = 0; par < 2; ++par) {
+      s->cur = par;
+      hipGraph_t g = nullptr;
+      HD_HIP(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
+      hd_status er = HD_OK;
+      for (int st = 0; st < 5 && er == HD_OK; ++st) er = enqueue_stage(s, st, dt, s->cap);
+      hipError_t ee = hipStreamEndCapture(s->cap, &g);
+      if (er != HD_OK) {
+        if (g) hipGraphDestroy(g);
+        s->cur = cur0;
+        return er;
+      }
+      if (ee != hipSuccess) {
+        s->cur = cur0;
+        return fail(HD_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ee));
+      }
+      hipError_t ei = hipGraphInstantiate(&s->gexec[par], g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (ei != hipSuccess) {
+        s->cur = cur0;
+        drop_graphs(s);
+        return fail(HD_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+      }
+    }
+    s->cur = cur0;
+    s->gdt = dt;
+    s->gvalid = true;
+  }
+  for (int i = 0; i < nsteps; ++i) {
+    HD_HIP(hipGraphLaunch(s->gexec[s->cur], (hipStream_t)stream));
+    s->cur = 1 - s->cur;  // five stages: the solution ends in the other buffer
+  }
+  return HD_OK;
+}
+
+hd_status hd_diagnostics(const hd_solver *s, double *mass, double *energy, hd_stream stream) {
+  hd_status r = check_bound(s);
+  if (r) return r;
+  if (!mass || !energy) return fail(HD_ERR_INVALID, "NULL argument");
+  const GeomArgs g = geom_of(s);
+  const long long chunk = (s->ndofs + kDiagBlocks - 1) / kDiagBlocks;
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(diag_kernel1, dim3(kDiagBlocks), dim3(kDiagThreads), 0, st, g, s->u(s->cur), chunk,
+                     s->part());
+  HD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(diag_kernel2, dim3(1), dim3(kDiagThreads), 0, st, s->part(), kDiagBlocks,
+                     s->part() + 2 * kDiagBlocks);
+  HD_HIP(hipGetLastError());
+  double res[2];
+  HD_HIP(hipMemcpyAsync(res, s->part() + 2 * kDiagBlocks, sizeof(res), hipMemcpyDeviceToHost, st));
+  HD_HIP(hipStreamSynchronize(st));
+  *mass = res[0];
+  *energy = res[1];
+  return HD_OK;
+}
+
+hd_status hd_get_plan(const hd_solver *s, hd_plan *plan) {
+  if (!s || !plan) return fail(HD_ERR_INVALID, "NULL argument");
+  *plan = s->plan;
+  return HD_OK;
+}
+
+hd_status hd_set_plan(hd_solver *s, const hd_plan *plan) {
+  if (!s || !plan) return fail(HD_ERR_INVALID, "NULL argument");
+  std::string why;
+  if (!valid_plan(s, *plan, &why)) return fail(HD_ERR_INVALID, why);
+  s->plan = *plan;
+  drop_graphs(s);
+  return HD_OK;
+}
+
+}  // extern "C"
+
+// Batched stepping is implemented in hd_batch.hip.

@@ -1,0 +1,304 @@
+// Fused element-centric DG advection stage kernel for gfx950.
+//
+// One thread owns a "pencil": the (k+1)^RD nodes of one cell that share the
+// thread's index in the NF = d - RD fastest node dimensions. Derivatives
+// along the RD slowest dimensions act on the thread's own registers;
+// derivatives along the NF fast dimensions read the other nodes of the line
+// from LDS (the cell is staged there once) or from global memory. Every
+// output value is written by exactly one thread and the input vector is
+// read-only, so the element-centric loop is race free (Sec. 2.6).
+//
+// Per node i of cell c the kernel evaluates, for each dimension j,
+//   -a_j/h_j * sum_m D[i_j][m] u_{i_j->m}                    (volume)
+//   + lift/h_j * max(a_j,0) * (u^-_{c-e_j} - u_i)  if i_j = 0   (inflow face)
+//   - lift/h_j * min(a_j,0) * (u^+_{c+e_j} - u_i)  if i_j = k   (inflow face)
+// with D[q][m] = l'_m(xi_q) and lift = 1/w_0 = 1/w_k. This is the strong
+// form of the collocated weak form of Sec. 1.3 / Algorithm 2: for
+// Gauss-Lobatto collocation the summation-by-parts identity
+// W D + D^T W = diag(-1, 0, .., 0, 1) turns the weak volume term plus the
+// outflow (own-trace) face terms into -a D u, leaving only the jump on the
+// inflow face. The inverse mass matrix is diagonal (collocation) and is
+// folded into the coefficients. a_j never depends on x_j for the supported
+// fields (constant; a_x = v, a_v = E(x)), so a_j factors out of the line sum.
+//
+// The low-storage RK update (Sec. 5.4) is fused into the same pass:
+//   du <- A_s du + dt L(u),  u_out <- u_in + B_s du.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hd {
+
+constexpr int kMaxN = 6;   // degree <= 5
+constexpr int kMaxD = 6;
+
+constexpr int ipow(int b, int e) {
+  int r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+// Kernel parameters, typed on the operator precision P.
+template <typename P>
+struct StageParams {
+  const double *u_in;   // FP64 solution in
+  double *u_out;        // FP64 solution out (stage mode)
+  P *du;                // stage increment (read if read_du, written if write_du)
+  P *out;               // operator output (apply mode)
+  const P *E;           // E at x-nodes: [(xcell * n^dx + xnode) * dx + comp]
+  unsigned ncells;
+  unsigned nblocks;     // blocks launched (for the XCD remap)
+  unsigned cells_per_wg;
+  unsigned cells[kMaxD];
+  unsigned cstride[kMaxD];
+  int mode;             // 0: out = L(u_in); 1: fused RK stage
+  int read_du, write_du;
+  int field_kind;       // 0: constant; 1: phase space
+  int xcd_remap;
+  double rk_b;          // B_s (FP64: applied to the FP64 solution)
+  P rk_a;               // A_s
+  P dt;
+  P inv_h[kMaxD];
+  P lift_inv_h[kMaxD];  // lift / h_j
+  P a_const[kMaxD];
+  P vlo[kMaxD], vh[kMaxD];  // node coordinate lo_j + (c_j + xi_i) h_j
+  P xi[kMaxN];
+  P Dm[kMaxN * kMaxN];  // Dm[q * N + m] = l'_m(xi_q) on [0, 1]
+  P esign;
+};
+
+// Map the hardware workgroup id (dispatched round-robin over the 8 XCDs) to a
+// tile index so that each XCD processes one contiguous range of tiles; the
+// face neighbours along the fast cell dimensions then share that XCD's L2.
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nblocks) {
+  const unsigned x = b & 7u, idx = b >> 3;
+  const unsigned q = nblocks >> 3, r = nblocks & 7u;
+  return x * q + (x < r ? x : r) + idx;
+}
+
+template <typename P>
+__device__ __forceinline__ P to_p(double v) {
+  return static_cast<P>(v);
+}
+
+// Largest workgroup a variant is launched with: 256 threads, except the LDS
+// variant of cells with more than 256 pencils (one cell per workgroup).
+template <int D, int N, int RD, bool USE_LDS>
+constexpr int stage_max_threads() {
+  return (USE_LDS && ipow(N, D - RD) > 256) ? 1024 : 256;
+}
+
+template <int D, int N, int DX, int RD, typename P, bool USE_LDS>
+__global__ void __launch_bounds__((stage_max_threads<D, N, RD, USE_LDS>()))
+    stage_kernel(const StageParams<P> prm) {
+  constexpr int DV = D - DX;
+  static_assert(RD >= 1 && RD <= DV, "register dims must be velocity dims");
+  constexpr int NF = D - RD;          // thread-distributed (fast) dims
+  constexpr int ND = ipow(N, D);      // nodes per cell
+  constexpr int T = ipow(N, NF);      // threads per cell
+  constexpr int NS = ipow(N, RD);     // nodes per thread
+  static_assert(DX <= NF, "all x dims are thread-distributed");
+
+  extern __shared__ unsigned char smem_raw[];
+  P *lds = reinterpret_cast<P *>(smem_raw);
+
+  unsigned tile = blockIdx.x;
+  if (prm.xcd_remap) tile = xcd_tile(tile, prm.nblocks);
+  unsigned cell, f, lc = 0;
+  if constexpr (USE_LDS) {
+    lc = threadIdx.x / T;
+    f = threadIdx.x - lc * T;
+    cell = tile * prm.cells_per_wg + lc;
+  } else {
+    const uint64_t p = (uint64_t)tile * blockDim.x + threadIdx.x;
+    cell = (unsigned)(p / T);
+    f = (unsigned)(p - (uint64_t)cell * T);
+  }
+  const bool active = cell < prm.ncells;
+  if constexpr (!USE_LDS) {
+    if (!active) return;
+  }
+  const unsigned cl = active ? cell : 0u;
+
+  // Cell multi-index.
+  unsigned c[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) c[j] = (cl / prm.cstride[j]) % prm.cells[j];
+  // Fast node digits of this thread.
+  int fd[NF > 0 ? NF : 1];
+  {
+    unsigned r = f;
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+      fd[j] = (int)(r % N);
+      r /= N;
+    }
+  }
+
+  const uint64_t base = (uint64_t)cl * ND + f;
+  P u[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) u[s] = to_p<P>(prm.u_in[base + (uint64_t)s * T]);
+  const bool stage = prm.mode == 1;
+  if constexpr (USE_LDS) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) lds[lc * ND + f + s * T] = u[s];
+    __syncthreads();
+    if (!active) return;
+  }
+
+  // Field at this thread's nodes. x dims are all fast, so E is per thread.
+  P ev[DV];
+  P vth[DX];   // velocity for x-dim j if its velocity dim is fast
+  P vbase[DX]; // lo + c h for x-dim j if its velocity dim is slow
+  const bool phase = prm.field_kind == 1;
+  if (phase) {
+    unsigned xcell = 0, xs = 1, xnode = 0, ns = 1;
+#pragma unroll
+    for (int m = 0; m < DX; ++m) {
+      xcell += c[m] * xs;
+      xs *= prm.cells[m];
+      xnode += fd[m] * ns;
+      ns *= N;
+    }
+    const P *e = prm.E + ((uint64_t)xcell * ipow(N, DX) + xnode) * DX;
+#pragma unroll
+    for (int j = 0; j < DV; ++j) ev[j] = prm.esign * e[j];
+#pragma unroll
+    for (int j = 0; j < DX; ++j) {
+      const int m = DX + j;
+      vbase[j] = prm.vlo[m] + P(c[m]) * prm.vh[m];
+      if (m < NF) vth[j] = vbase[j] + prm.xi[fd[m]] * prm.vh[m];
+      else vth[j] = P(0);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < DV; ++j) ev[j] = prm.a_const[DX + j];
+#pragma unroll
+    for (int j = 0; j < DX; ++j) {
+      vth[j] = prm.a_const[j];
+      vbase[j] = prm.a_const[j];
+    }
+  }
+  // a_j at the thread's node s (compile-time j and s after unrolling).
+  auto a_at = [&](int j, int s) -> P {
+    if (j >= DX) return ev[j - DX];
+    const int m = DX + j;
+    if (!phase || m < NF) return vth[j];
+    const int r = m - NF;
+    const int dig = (s / ipow(N, r)) % N;
+    return vbase[j] + prm.xi[dig] * prm.vh[m];
+  };
+
+  P acc[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) acc[s] = P(0);
+
+  // ---- fast (thread-distributed) dimensions ----
+#pragma unroll
+  for (int j = 0; j < NF; ++j) {
+    const int ij = fd[j];
+    const int stride = ipow(N, j);
+    P row[N];
+#pragma unroll
+    for (int m = 0; m < N; ++m) row[m] = prm.Dm[ij * N + m];
+    const int off0 = (int)f - ij * stride;  // node offset of digit j = 0
+    const P ih = prm.inv_h[j];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      P sum = P(0);
+#pragma unroll
+      for (int m = 0; m < N; ++m) {
+        P v;
+        if constexpr (USE_LDS) v = lds[lc * ND + off0 + m * stride + s * T];
+        else v = to_p<P>(prm.u_in[(uint64_t)cl * ND + off0 + m * stride + (uint64_t)s * T]);
+        sum += row[m] * v;
+      }
+      acc[s] -= a_at(j, s) * ih * sum;
+    }
+    // Inflow face: the only place the neighbour's trace enters.
+    const P lf = prm.lift_inv_h[j];
+    if (ij == 0 || ij == N - 1) {
+      const unsigned cj = c[j], nj = prm.cells[j], st = prm.cstride[j];
+      const unsigned left = cj == 0 ? cl + (nj - 1) * st : cl - st;
+      const unsigned right = cj == nj - 1 ? cl - (nj - 1) * st : cl + st;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const P a = a_at(j, s);
+        if (ij == 0 && a > P(0)) {
+          const P nb = to_p<P>(prm.u_in[(uint64_t)left * ND + f + (N - 1) * stride + (uint64_t)s * T]);
+          acc[s] += lf * a * (nb - u[s]);
+        } else if (ij == N - 1 && a < P(0)) {
+          const P nb = to_p<P>(prm.u_in[(uint64_t)right * ND + f - (N - 1) * stride + (uint64_t)s * T]);
+          acc[s] -= lf * a * (nb - u[s]);
+        }
+      }
+    }
+  }
+
+  // ---- slow (register) dimensions ----
+#pragma unroll
+  for (int r = 0; r < RD; ++r) {
+    const int j = NF + r;
+    const int sstride = ipow(N, r);
+    const P ih = prm.inv_h[j];
+    const P lf = prm.lift_inv_h[j];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int ij = (s / sstride) % N;
+      const int s0 = s - ij * sstride;
+      P sum = P(0);
+#pragma unroll
+      for (int m = 0; m < N; ++m) sum += prm.Dm[ij * N + m] * u[s0 + m * sstride];
+      acc[s] -= a_at(j, s) * ih * sum;
+    }
+    const unsigned cj = c[j], nj = prm.cells[j], st = prm.cstride[j];
+    const unsigned left = cj == 0 ? cl + (nj - 1) * st : cl - st;
+    const unsigned right = cj == nj - 1 ? cl - (nj - 1) * st : cl + st;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int ij = (s / sstride) % N;
+      if (ij != 0) continue;  // one line per s with digit 0
+      const P a = a_at(j, s);
+      const int sk = s + (N - 1) * sstride;
+      if (a > P(0)) {
+        const P nb = to_p<P>(prm.u_in[(uint64_t)left * ND + f + (uint64_t)sk * T]);
+        acc[s] += lf * a * (nb - u[s]);
+      } else if (a < P(0)) {
+        const P nb = to_p<P>(prm.u_in[(uint64_t)right * ND + f + (uint64_t)s * T]);
+        acc[sk] -= lf * a * (nb - u[sk]);
+      }
+    }
+  }
+
+  // ---- output ----
+  if (!stage) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) prm.out[base + (uint64_t)s * T] = acc[s];
+    return;
+  }
+  // The increment is read only now, keeping registers free during the sweeps.
+  P dv[NS];
+  if (prm.read_du) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) dv[s] = prm.du[base + (uint64_t)s * T];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) dv[s] = prm.rk_a * dv[s] + prm.dt * acc[s];
+  } else {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) dv[s] = prm.dt * acc[s];
+  }
+  if (prm.write_du) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) prm.du[base + (uint64_t)s * T] = dv[s];
+  }
+  // FP64 solution update; in FP32 mode the FP64 input is re-read (cache hit).
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const double uo = sizeof(P) == sizeof(double) ? (double)u[s] : prm.u_in[base + (uint64_t)s * T];
+    prm.u_out[base + (uint64_t)s * T] = uo + prm.rk_b * (double)dv[s];
+  }
+}
+
+}  // namespace hd

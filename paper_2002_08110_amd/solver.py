@@ -1,0 +1,170 @@
+"""Thin object wrapper over the C ABI: a Solver owns an hd_solver handle and
+a torch device tensor as its workspace. Only marshalling happens here; every
+computation is a HIP kernel in libhd.so. PyTorch supplies device memory and
+the current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _hd
+from ._hd import check, hd_mesh, hd_plan
+
+_ALIGN = 256
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_mesh(dim_x, dim_v, cells, lo, hi) -> hd_mesh:
+    m = hd_mesh()
+    m.dim_x, m.dim_v = int(dim_x), int(dim_v)
+    for j in range(dim_x + dim_v):
+        m.cells[j] = int(cells[j])
+        m.lo[j] = float(lo[j])
+        m.hi[j] = float(hi[j])
+    return m
+
+
+class Solver:
+    """hd_create + hd_bind over a torch-allocated workspace on `device`."""
+
+    def __init__(self, dim_x, dim_v, cells, lo, hi, degree, precision="fp64",
+                 device="cuda:0", bind=True):
+        self.lib = _hd.load()
+        self.dim_x, self.dim_v, self.k = int(dim_x), int(dim_v), int(degree)
+        self.d = self.dim_x + self.dim_v
+        self.cells = [int(c) for c in cells[: self.d]]
+        self.lo = [float(x) for x in lo[: self.d]]
+        self.hi = [float(x) for x in hi[: self.d]]
+        self.precision = precision
+        self.prec = _hd.HD_FP32 if precision == "fp32" else _hd.HD_FP64
+        self.device = torch.device(device)
+        self.mesh = make_mesh(dim_x, dim_v, cells, lo, hi)
+        h = ctypes.c_void_p()
+        check(self.lib.hd_create(ctypes.byref(self.mesh), self.k, self.prec, ctypes.byref(h)))
+        self.h = h
+        n = ctypes.c_int64()
+        check(self.lib.hd_num_dofs(self.h, ctypes.byref(n)))
+        self.ndofs = n.value
+        b = ctypes.c_size_t()
+        check(self.lib.hd_required_bytes(self.h, ctypes.byref(b)))
+        self.workspace_bytes = b.value
+        self.workspace = None
+        if bind:
+            self.bind()
+
+    # -- memory -----------------------------------------------------------
+    def bind(self, workspace: torch.Tensor | None = None):
+        if workspace is None:
+            workspace = torch.empty(self.workspace_bytes + _ALIGN, dtype=torch.uint8,
+                                    device=self.device)
+        off = (-workspace.data_ptr()) % _ALIGN
+        self._ws_raw = workspace
+        self.workspace = workspace[off: off + self.workspace_bytes]
+        check(self.lib.hd_bind(self.h, ctypes.c_void_p(self.workspace.data_ptr()),
+                               self.workspace_bytes))
+
+    def state_ptr(self) -> int:
+        p = ctypes.c_void_p()
+        check(self.lib.hd_state_ptr(self.h, ctypes.byref(p)))
+        return p.value
+
+    def state_tensor(self) -> torch.Tensor:
+        """A float64 view of the current solution inside the workspace."""
+        off = self.state_ptr() - self.workspace.data_ptr()
+        return self.workspace[off: off + 8 * self.ndofs].view(torch.float64)
+
+    # -- field ------------------------------------------------------------
+    def set_field_constant(self, a):
+        arr = (ctypes.c_double * 6)(*([float(x) for x in a] + [0.0] * (6 - len(a))))
+        check(self.lib.hd_set_field_constant(self.h, arr))
+
+    def set_field_sine(self, amp=0.1, sign=1.0):
+        check(self.lib.hd_set_field_sine(self.h, float(amp), float(sign)))
+
+    def set_field_phase_space(self, E, sign=1.0):
+        E = np.ascontiguousarray(E, dtype=np.float64)
+        check(self.lib.hd_set_field_phase_space(
+            self.h, E.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(sign)))
+
+    # -- state ------------------------------------------------------------
+    def set_state(self, u, stream=None):
+        if isinstance(u, torch.Tensor):
+            assert u.dtype == torch.float64 and u.is_contiguous() and u.numel() == self.ndofs
+            if u.is_cuda:
+                check(self.lib.hd_set_state(self.h, ctypes.c_void_p(u.data_ptr()), 1,
+                                            _stream(stream)))
+                return
+            u = u.numpy()
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        assert u.size == self.ndofs
+        check(self.lib.hd_set_state(self.h, ctypes.c_void_p(u.ctypes.data), 0, _stream(stream)))
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+
+    def init_state(self, kind, params=None, stream=None):
+        p = (ctypes.c_double * 1)(float(params[0]) if params else 0.0)
+        check(self.lib.hd_init_state(self.h, int(kind), p, _stream(stream)))
+
+    def get_state(self, stream=None) -> np.ndarray:
+        out = np.empty(self.ndofs, dtype=np.float64)
+        check(self.lib.hd_get_state(self.h, ctypes.c_void_p(out.ctypes.data), _stream(stream)))
+        return out
+
+    # -- operator and time stepping ---------------------------------------
+    def apply(self, inp: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+        assert inp.dtype == torch.float64 and inp.is_cuda and inp.is_contiguous()
+        assert inp.numel() == self.ndofs
+        odt = torch.float32 if self.prec == _hd.HD_FP32 else torch.float64
+        if out is None:
+            out = torch.empty(self.ndofs, dtype=odt, device=inp.device)
+        assert out.dtype == odt and out.is_contiguous() and out.numel() == self.ndofs
+        check(self.lib.hd_apply(self.h, ctypes.c_void_p(inp.data_ptr()),
+                                ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
+
+    def stable_dt(self, cfl=0.2) -> float:
+        dt = ctypes.c_double()
+        check(self.lib.hd_stable_dt(self.h, float(cfl), ctypes.byref(dt)))
+        return dt.value
+
+    def rk_stage(self, stage, dt, stream=None):
+        check(self.lib.hd_rk_stage(self.h, int(stage), float(dt), _stream(stream)))
+
+    def rk_step(self, dt, nsteps=1, stream=None):
+        check(self.lib.hd_rk_step(self.h, float(dt), int(nsteps), _stream(stream)))
+
+    def diagnostics(self, stream=None):
+        m = ctypes.c_double()
+        e = ctypes.c_double()
+        check(self.lib.hd_diagnostics(self.h, ctypes.byref(m), ctypes.byref(e), _stream(stream)))
+        return m.value, e.value
+
+    # -- plan -------------------------------------------------------------
+    def get_plan(self) -> dict:
+        p = hd_plan()
+        check(self.lib.hd_get_plan(self.h, ctypes.byref(p)))
+        return p.as_dict()
+
+    def set_plan(self, **kw):
+        p = hd_plan()
+        check(self.lib.hd_get_plan(self.h, ctypes.byref(p)))
+        for k, v in kw.items():
+            setattr(p, k, int(v))
+        check(self.lib.hd_set_plan(self.h, ctypes.byref(p)))
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.hd_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,82 @@
+"""Shared setup for the GPU parity tests: build the oracle problem and the
+HIP solver for the same seeded workload. The two sides share only the
+workload description (paper_2002_08110_amd.workloads) and the seeded input
+arrays; each computes its own nodes, field tables and operator.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+from paper_2002_08110_amd import workloads as W
+
+# FP64 parity bar: relative L2 difference to the oracle (and the same bound on
+# the max-norm relative to the reference's max) of at most 1e-12.
+TOL_FP64 = 1e-12
+
+
+def rel_l2(got, ref):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def rel_max(got, ref):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+def oracle_problem(case: W.Case, E=None, sign=1.0):
+    if case.field == "constant":
+        return oracle.Problem(case.dim_x, case.dim_v, case.cells, case.lo, case.hi, case.degree,
+                              field="constant", a=case.a)
+    if case.field == "sine":
+        return oracle.Problem(case.dim_x, case.dim_v, case.cells, case.lo, case.hi, case.degree,
+                              field="phase", sine_amp=case.amp, sign=sign)
+    if case.field == "table":
+        return oracle.Problem(case.dim_x, case.dim_v, case.cells, case.lo, case.hi, case.degree,
+                              field="phase", E=E, sign=sign)
+    raise ValueError(case.field)
+
+
+def gpu_solver(case: W.Case, precision="fp64", E=None, sign=1.0, plan=None):
+    from paper_2002_08110_amd.solver import Solver
+    s = Solver(case.dim_x, case.dim_v, case.cells, case.lo, case.hi, case.degree,
+               precision=precision)
+    if case.field == "constant":
+        s.set_field_constant(case.a)
+    elif case.field == "sine":
+        s.set_field_sine(case.amp, sign)
+    elif case.field == "table":
+        s.set_field_phase_space(E, sign)
+    if plan:
+        s.set_plan(**plan)
+    return s
+
+
+def x_table_size(case: W.Case):
+    return int(np.prod(case.cells[: case.dim_x])) * (case.degree + 1) ** case.dim_x * case.dim_x
+
+
+def all_plans(case: W.Case, precision="fp64"):
+    """Every valid launch plan of the stage kernel for this case."""
+    n = case.degree + 1
+    d = case.d
+    psize = 4 if precision == "fp32" else 8
+    nd = n ** d
+    plans = []
+    for rd in (1, 2):
+        if rd > case.dim_v:
+            continue
+        T = n ** (d - rd)
+        for xcd in (0, 1):
+            for wg in (64, 256):
+                plans.append(dict(lds=0, wg_size=wg, reg_dims=rd, xcd_remap=xcd, cells_per_wg=1))
+            if T <= 1024 and nd * psize <= 160 * 1024:
+                cpws = [1] if T > 256 else sorted({1, max(1, 256 // T)})
+                for cpw in cpws:
+                    if cpw * nd * psize <= 160 * 1024:
+                        plans.append(dict(lds=1, cells_per_wg=cpw, reg_dims=rd, xcd_remap=xcd,
+                                          wg_size=256))
+    return plans

@@ -1,0 +1,105 @@
+"""CPU-only checks of the C ABI library: it loads without a GPU, exports every
+entry point include/hd.h declares, and rejects invalid descriptors. No
+compute call is made here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2002_08110_amd import _hd
+    if not os.path.exists(_hd.LIB_PATH):
+        from paper_2002_08110_amd import build
+        build.build()
+    return _hd.load()
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "hd.h")).read()
+    return sorted(set(re.findall(r"\b(hd_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib()
+    names = declared_symbols()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_2002_08110_amd._hd import SYMBOLS
+    assert sorted(SYMBOLS) == names
+
+
+def _mesh(dx, dv, cells, lo=None, hi=None):
+    from paper_2002_08110_amd._hd import hd_mesh
+    m = hd_mesh()
+    m.dim_x, m.dim_v = dx, dv
+    d = dx + dv
+    for j in range(d):
+        m.cells[j] = cells[j]
+        m.lo[j] = 0.0 if lo is None else lo[j]
+        m.hi[j] = 1.0 if hi is None else hi[j]
+    return m
+
+
+@pytest.mark.parametrize("dx,dv,cells,k,prec,status", [
+    (0, 1, [1, 1], 3, 0, -1), (1, 4, [1] * 5, 3, 0, -1), (1, 1, [0, 2], 3, 0, -1),
+    (1, 1, [2, 2], 0, 0, -1), (1, 1, [2, 2], 6, 0, -2), (1, 1, [2, 2], 3, 7, -1),
+    (1, 2, [2, 2, 2], 3, 0, -2), (3, 3, [8] * 6, 3, 0, 0), (3, 3, [8] * 6, 5, 1, 0),
+])
+def test_create_validates_descriptors(dx, dv, cells, k, prec, status):
+    lib = _lib()
+    m = _mesh(dx, dv, cells)
+    h = ctypes.c_void_p()
+    r = lib.hd_create(ctypes.byref(m), k, prec, ctypes.byref(h))
+    assert r == status, lib.hd_last_error()
+    if r == 0:
+        lib.hd_destroy(h)
+    else:
+        assert lib.hd_last_error()
+
+
+def test_lo_ge_hi_rejected_and_sizes():
+    lib = _lib()
+    m = _mesh(1, 1, [2, 2], lo=[0, 1], hi=[1, 1])
+    h = ctypes.c_void_p()
+    assert lib.hd_create(ctypes.byref(m), 2, 0, ctypes.byref(h)) == -1
+    m = _mesh(3, 3, [8] * 6)
+    assert lib.hd_create(ctypes.byref(m), 3, 0, ctypes.byref(h)) == 0
+    n = ctypes.c_int64()
+    b = ctypes.c_size_t()
+    assert lib.hd_num_dofs(h, ctypes.byref(n)) == 0 and n.value == 8 ** 6 * 4 ** 6
+    assert lib.hd_required_bytes(h, ctypes.byref(b)) == 0
+    # two FP64 solution buffers + FP64 du (3 vectors, Sec. 5.4) + small tables
+    assert 3 * 8 * n.value <= b.value < 3 * 8 * n.value + (1 << 22)
+    # calls that need bound memory fail cleanly before hd_bind
+    dt = ctypes.c_double()
+    assert lib.hd_rk_step(h, ctypes.c_double(1e-3), 1, None) == -1
+    assert lib.hd_stable_dt(h, ctypes.c_double(0.2), ctypes.byref(dt)) == -1  # zero field
+    lib.hd_destroy(h)
+    m = _mesh(3, 3, [8] * 6)
+    assert lib.hd_create(ctypes.byref(m), 3, 1, ctypes.byref(h)) == 0
+    assert lib.hd_required_bytes(h, ctypes.byref(b)) == 0
+    assert 20 * n.value <= b.value < 20 * n.value + (1 << 22)  # FP32 du
+    lib.hd_destroy(h)
+
+
+def test_plan_validation_without_gpu():
+    from paper_2002_08110_amd._hd import hd_plan
+    lib = _lib()
+    m = _mesh(3, 3, [8] * 6)
+    h = ctypes.c_void_p()
+    assert lib.hd_create(ctypes.byref(m), 3, 0, ctypes.byref(h)) == 0
+    p = hd_plan()
+    assert lib.hd_get_plan(h, ctypes.byref(p)) == 0
+    assert p.reg_dims in (1, 2)
+    q = hd_plan(lds=1, cells_per_wg=2, wg_size=256, xcd_remap=1, reg_dims=1)
+    assert lib.hd_set_plan(h, ctypes.byref(q)) == -1  # 2 x 1024 threads
+    q = hd_plan(lds=0, cells_per_wg=1, wg_size=100, xcd_remap=1, reg_dims=1)
+    assert lib.hd_set_plan(h, ctypes.byref(q)) == -1
+    q = hd_plan(lds=0, cells_per_wg=1, wg_size=128, xcd_remap=0, reg_dims=2)
+    assert lib.hd_set_plan(h, ctypes.byref(q)) == 0
+    lib.hd_destroy(h)
