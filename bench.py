@@ -92,7 +92,7 @@ def measure(case, precision, steps, warmup, plan_override):
     res = dict(
         precision=precision, ndofs=S.ndofs, dt=dt, ms_per_step=ms_step, wall_s=wall,
         dof_updates_per_s=S.ndofs * 5 / (ms_step * 1e-3),
-        stage_ms=[round(x, 4) for x in stage_ms],
+        stage_ms=[round(float(x), 4) for x in stage_ms],
         stage_kernel_GBps=achieved, algorithmic_bytes_per_dof=float(np.mean(stage_bytes(psize))),
         plan=S.get_plan(), mass_drift=(m1 - m0) / abs(m0), energy_ratio=e1 / e0,
     )

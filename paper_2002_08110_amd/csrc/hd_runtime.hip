@@ -118,7 +118,9 @@ hd_plan default_plan(const hd_solver *s) {
   hd_plan p{};
   p.xcd_remap = 1;
   p.wg_size = 256;
-  p.reg_dims = (s->n <= 3 && s->dv >= 2) ? 2 : 1;
+  // Measured on MI355X: FP64 prefers two register dimensions up to degree 3
+  // (16 nodes per thread), FP32 one.
+  p.reg_dims = (s->dv >= 2 && (s->n <= 3 || (s->n == 4 && s->prec == HD_FP64))) ? 2 : 1;
   int64_t T = 1;
   for (int j = 0; j < s->d - p.reg_dims; ++j) T *= s->n;
   const int64_t cell_bytes = s->nd * (int64_t)s->psize();

@@ -77,6 +77,10 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nblocks) {
   return x * q + (x < r ? x : r) + idx;
 }
 
+// Scheduling fence: keeps the compiler from hoisting the loads of later
+// dimensions above this point, which would multiply live registers.
+__device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
+
 template <typename P>
 __device__ __forceinline__ P to_p(double v) {
   return static_cast<P>(v);
@@ -195,11 +199,47 @@ __global__ void __launch_bounds__((stage_max_threads<D, N, RD, USE_LDS>()))
 #pragma unroll
   for (int s = 0; s < NS; ++s) acc[s] = P(0);
 
+  // Inflow-face loads are issued as unconditional batches (no branches
+  // around them): a node off the inflow face reads its own value, a cache
+  // hit, and gives it zero weight. Batching lets the loads of one
+  // dimension overlap the volume sweep that follows them.
+  // ---- slow (register) dimensions: face loads first ----
+  constexpr int NL = NS / N;  // lines per register dimension
+  P nbs[RD][NL];
+#pragma unroll
+  for (int r = 0; r < RD; ++r) {
+    const int j = NF + r;
+    const int sstride = ipow(N, r);
+    const unsigned cj = c[j], nj = prm.cells[j], st = prm.cstride[j];
+    const unsigned left = cj == 0 ? cl + (nj - 1) * st : cl - st;
+    const unsigned right = cj == nj - 1 ? cl - (nj - 1) * st : cl + st;
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const int s = (l % sstride) + (l / sstride) * sstride * N;  // digit r = 0
+      const int sk = s + (N - 1) * sstride;
+      const P a = a_at(j, s);
+      const bool useL = a > P(0), useR = a < P(0);
+      const unsigned cc = useL ? left : (useR ? right : cl);
+      const int sn = useL ? sk : s;
+      nbs[r][l] = to_p<P>(prm.u_in[(uint64_t)cc * ND + f + (uint64_t)sn * T]);
+    }
+  }
+  constexpr bool kPrefetchDu = sizeof(P) == 4 || NS <= 4;
+  P dv[NS];
+  if (kPrefetchDu && stage && prm.read_du) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) dv[s] = prm.du[base + (uint64_t)s * T];
+  }
+  sched_fence();
+
   // ---- fast (thread-distributed) dimensions ----
 #pragma unroll
   for (int j = 0; j < NF; ++j) {
     const int ij = fd[j];
     const int stride = ipow(N, j);
+    const unsigned cj = c[j], nj = prm.cells[j], st = prm.cstride[j];
+    const unsigned left = cj == 0 ? cl + (nj - 1) * st : cl - st;
+    const unsigned right = cj == nj - 1 ? cl - (nj - 1) * st : cl + st;
     P row[N];
 #pragma unroll
     for (int m = 0; m < N; ++m) row[m] = prm.Dm[ij * N + m];
@@ -217,24 +257,30 @@ __global__ void __launch_bounds__((stage_max_threads<D, N, RD, USE_LDS>()))
       }
       acc[s] -= a_at(j, s) * ih * sum;
     }
-    // Inflow face: the only place the neighbour's trace enters.
-    const P lf = prm.lift_inv_h[j];
+    // Inflow face: the only place the neighbour's trace enters. Only
+    // threads on a face of this dimension take part; their loads are
+    // issued as one batch before any is used.
     if (ij == 0 || ij == N - 1) {
-      const unsigned cj = c[j], nj = prm.cells[j], st = prm.cstride[j];
-      const unsigned left = cj == 0 ? cl + (nj - 1) * st : cl - st;
-      const unsigned right = cj == nj - 1 ? cl - (nj - 1) * st : cl + st;
+      const bool onL = ij == 0, onR = ij == N - 1;
+      P nb[NS];
+  #pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const P a = a_at(j, s);
+        const bool useL = onL && a > P(0), useR = onR && a < P(0);
+        const unsigned cc = useL ? left : (useR ? right : cl);
+        const int node = (int)f + (useL ? (N - 1) * stride : (useR ? -(N - 1) * stride : 0));
+        nb[s] = to_p<P>(prm.u_in[(uint64_t)cc * ND + node + (uint64_t)s * T]);
+      }
+      const P lf = prm.lift_inv_h[j];
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         const P a = a_at(j, s);
-        if (ij == 0 && a > P(0)) {
-          const P nb = to_p<P>(prm.u_in[(uint64_t)left * ND + f + (N - 1) * stride + (uint64_t)s * T]);
-          acc[s] += lf * a * (nb - u[s]);
-        } else if (ij == N - 1 && a < P(0)) {
-          const P nb = to_p<P>(prm.u_in[(uint64_t)right * ND + f - (N - 1) * stride + (uint64_t)s * T]);
-          acc[s] -= lf * a * (nb - u[s]);
-        }
+        const bool useL = onL && a > P(0), useR = onR && a < P(0);
+        const P w = useL ? lf * a : (useR ? -lf * a : P(0));
+        acc[s] += w * (nb[s] - u[s]);
       }
     }
+    sched_fence();
   }
 
   // ---- slow (register) dimensions ----
@@ -253,22 +299,15 @@ __global__ void __launch_bounds__((stage_max_threads<D, N, RD, USE_LDS>()))
       for (int m = 0; m < N; ++m) sum += prm.Dm[ij * N + m] * u[s0 + m * sstride];
       acc[s] -= a_at(j, s) * ih * sum;
     }
-    const unsigned cj = c[j], nj = prm.cells[j], st = prm.cstride[j];
-    const unsigned left = cj == 0 ? cl + (nj - 1) * st : cl - st;
-    const unsigned right = cj == nj - 1 ? cl - (nj - 1) * st : cl + st;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      const int ij = (s / sstride) % N;
-      if (ij != 0) continue;  // one line per s with digit 0
-      const P a = a_at(j, s);
+    for (int l = 0; l < NL; ++l) {
+      const int s = (l % sstride) + (l / sstride) * sstride * N;
       const int sk = s + (N - 1) * sstride;
-      if (a > P(0)) {
-        const P nb = to_p<P>(prm.u_in[(uint64_t)left * ND + f + (uint64_t)sk * T]);
-        acc[s] += lf * a * (nb - u[s]);
-      } else if (a < P(0)) {
-        const P nb = to_p<P>(prm.u_in[(uint64_t)right * ND + f + (uint64_t)s * T]);
-        acc[sk] -= lf * a * (nb - u[sk]);
-      }
+      const P a = a_at(j, s);
+      const P wL = a > P(0) ? lf * a : P(0);
+      const P wR = a < P(0) ? -lf * a : P(0);
+      acc[s] += wL * (nbs[r][l] - u[s]);
+      acc[sk] += wR * (nbs[r][l] - u[sk]);
     }
   }
 
@@ -278,11 +317,13 @@ __global__ void __launch_bounds__((stage_max_threads<D, N, RD, USE_LDS>()))
     for (int s = 0; s < NS; ++s) prm.out[base + (uint64_t)s * T] = acc[s];
     return;
   }
-  // The increment is read only now, keeping registers free during the sweeps.
-  P dv[NS];
+  // FP64 with many nodes per thread reads the increment only now, keeping
+  // registers free during the sweeps.
   if (prm.read_du) {
+    if (!kPrefetchDu) {
 #pragma unroll
-    for (int s = 0; s < NS; ++s) dv[s] = prm.du[base + (uint64_t)s * T];
+      for (int s = 0; s < NS; ++s) dv[s] = prm.du[base + (uint64_t)s * T];
+    }
 #pragma unroll
     for (int s = 0; s < NS; ++s) dv[s] = prm.rk_a * dv[s] + prm.dt * acc[s];
   } else {

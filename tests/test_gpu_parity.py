@@ -63,16 +63,20 @@ def test_apply_matches_oracle_fp64(d, k, field):
     ref = P.apply(u)
     S = gpu_solver(case, "fp64", E=E, sign=-1.0 if field == "table" else 1.0)
     ut = torch.from_numpy(u).cuda()
-    outs = []
+    outs = {}
     for plan in all_plans(case):
         S.set_plan(**plan)
         out = S.apply(ut).cpu().numpy()
         assert rel_l2(out, ref) <= TOL_FP64, plan
         assert rel_max(out, ref) <= TOL_FP64, plan
-        outs.append(out)
-    # Every launch plan evaluates each output with the same arithmetic.
-    for o in outs[1:]:
-        assert np.array_equal(o, outs[0])
+        outs.setdefault(plan["reg_dims"], []).append(out)
+    # Plans with the same register dims evaluate each output with the same
+    # arithmetic whatever the schedule (LDS or global reads, cells per
+    # workgroup, XCD remap), so they agree bitwise; no output depends on
+    # which workgroup computed it.
+    for group in outs.values():
+        for o in group[1:]:
+            assert np.array_equal(o, group[0])
 
 
 @pytest.mark.parametrize("d,k", [(2, 3), (3, 2), (4, 3), (5, 2), (6, 3), (6, 5)])
@@ -117,7 +121,7 @@ def test_config_2d_rk_matches_oracle_and_exact_solution():
 
 
 @pytest.mark.parametrize("d,k,cells,steps", [(4, 3, [3, 2, 2, 3], 3), (6, 3, [2] * 6, 2),
-                                             (5, 2, [2, 3, 1, 2, 3], 2), (6, 2, [3, 2, 1, 2, 1, 3], 2)])
+                                             (2, 4, [5, 3], 4), (6, 2, [3, 2, 1, 2, 1, 3], 2)])
 def test_phase_space_rk_matches_oracle(d, k, cells, steps):
     dx, dv = W.SPLITS[d]
     case = W.phase_space_case("p", dx, dv, cells, k, steps)
@@ -136,6 +140,22 @@ def test_phase_space_rk_matches_oracle(d, k, cells, steps):
     m, e = S.diagnostics()
     mo, eo = P.diagnostics(ref)
     assert abs(m - mo) <= 1e-13 * abs(mo) and abs(e - eo) <= 1e-12 * eo
+
+
+@pytest.mark.parametrize("d,k,cells", [(5, 2, [2, 3, 1, 2, 3]), (3, 3, [4, 3, 5]), (5, 4, [1, 2, 1, 2, 2])])
+def test_constant_field_rk_matches_oracle(d, k, cells):
+    dx, dv = W.SPLITS[d]
+    rng = np.random.default_rng(d + k)
+    case = W.Case("c", dx, dv, cells, [0.0] * d, [1.0] * d, k, "constant",
+                  a=list(rng.uniform(-1, 1, d)), ic=0, steps=3)
+    P = oracle_problem(case)
+    S = gpu_solver(case, "fp64")
+    dt = S.stable_dt(case.cfl)
+    u0 = W.random_state(P.ndofs, seed=4)
+    S.set_state(u0)
+    S.rk_step(dt, case.steps)
+    ref = P.rk_steps(u0, dt, case.steps)
+    assert rel_l2(S.get_state(), ref) <= TOL_FP64
 
 
 def test_graph_replay_is_bitwise_equal_to_direct_stages():
