@@ -78,13 +78,17 @@ typedef struct hd_batch hd_batch;    /* opaque */
  *  wg_size:    threads per workgroup for lds = 0 (multiple of 64, <= 1024).
  *  xcd_remap:  1 = map consecutive cell tiles to the same XCD.
  *  reg_dims:   number of slowest dimensions whose lines a thread keeps in
- *              registers (1 or 2; at most dim_v). */
+ *              registers (1 or 2; at most dim_v).
+ *  kernel:     0 = the generic kernel (the fields above apply); 1 = the
+ *              kernel specialised for d = 6 (3 x + 3 v) at degree 3, one cell
+ *              per 256-thread workgroup (only xcd_remap applies). */
 typedef struct {
   int lds;
   int cells_per_wg;
   int wg_size;
   int xcd_remap;
   int reg_dims;
+  int kernel;
 } hd_plan;
 
 /* Create a solver for `mesh` and polynomial degree `degree` (k+1 nodes per

@@ -15,6 +15,7 @@
 #include "gl_tables.h"
 #include "hd.h"
 #include "stage_dispatch.h"
+#include "stage_k3.h"
 
 namespace {
 
@@ -82,7 +83,24 @@ struct hd_solver {
 
 namespace {
 
+// The specialised kernel covers d = 6 (3 x + 3 v) at degree 3.
+// Its in-kernel neighbour offsets are 32-bit DoF counts: fewer than 2^31 DoFs.
+bool k3_eligible(const hd_solver *s) {
+  return s->d == 6 && s->dx == 3 && s->n == 4 && s->ndofs < (int64_t(1) << 31);
+}
+
 bool valid_plan(const hd_solver *s, const hd_plan &p, std::string *why) {
+  if (p.kernel != 0 && p.kernel != 1) {
+    *why = "kernel must be 0 (generic) or 1 (6D degree-3)";
+    return false;
+  }
+  if (p.kernel == 1) {
+    if (!k3_eligible(s)) {
+      *why = "kernel 1 needs d = 6 (3 x + 3 v) and degree 3";
+      return false;
+    }
+    return true;
+  }
   const int rd = p.reg_dims;
   if (rd < 1 || rd > 2 || rd > s->dv) {
     *why = "reg_dims must be 1 or 2 and at most dim_v";
@@ -133,6 +151,7 @@ hd_plan default_plan(const hd_solver *s) {
     p.lds = 0;
     p.cells_per_wg = 1;
   }
+  p.kernel = k3_eligible(s) ? 1 : 0;
   return p;
 }
 
@@ -159,10 +178,26 @@ void fill_params(const hd_solver *s, hd::StageParams<P> *prm) {
   prm->E = reinterpret_cast<const P *>(s->E());
   prm->xcd_remap = s->plan.xcd_remap;
   prm->cells_per_wg = (unsigned)s->plan.cells_per_wg;
+  if (s->plan.kernel == 1 && s->field_kind == 0) {
+    // The specialised kernel reads every field in phase-space form: the
+    // constant a_x as a velocity coordinate with zero cell width, the
+    // constant a_v from the E table (filled with the constants).
+    for (int j = 0; j < s->dx; ++j) {
+      prm->vlo[s->dx + j] = (P)s->a_const[j];
+      prm->vh[s->dx + j] = P(0);
+    }
+    prm->esign = P(1);
+  }
 }
 
 hd::LaunchShape shape_of(const hd_solver *s) {
   hd::LaunchShape ls{};
+  if (s->plan.kernel == 1) {
+    ls.grid = (unsigned)s->ncells;
+    ls.block = 256;
+    ls.shmem = s->prec == HD_FP32 ? hd::k3_lds_bytes<float>() : hd::k3_lds_bytes<double>();
+    return ls;
+  }
   int64_t T = 1;
   for (int j = 0; j < s->d - s->plan.reg_dims; ++j) T *= s->n;
   if (s->plan.lds) {
@@ -186,6 +221,7 @@ hipError_t dispatch(const hd_solver *s, const hd::StageParams<P> &prm, const hd:
 template <>
 hipError_t dispatch<double>(const hd_solver *s, const hd::StageParams<double> &prm,
                             const hd::LaunchShape &ls, hipStream_t st) {
+  if (s->plan.kernel == 1) return hd::stage_k3_f64(prm, ls.grid, st);
   const int rd = s->plan.reg_dims, lds = s->plan.lds, n = s->n;
   switch (s->d) {
     case 2: return hd::stage_d2_f64(n, rd, lds, prm, ls, st);
@@ -200,6 +236,7 @@ hipError_t dispatch<double>(const hd_solver *s, const hd::StageParams<double> &p
 template <>
 hipError_t dispatch<float>(const hd_solver *s, const hd::StageParams<float> &prm,
                            const hd::LaunchShape &ls, hipStream_t st) {
+  if (s->plan.kernel == 1) return hd::stage_k3_f32(prm, ls.grid, st);
   const int rd = s->plan.reg_dims, lds = s->plan.lds, n = s->n;
   switch (s->d) {
     case 2: return hd::stage_d2_f32(n, rd, lds, prm, ls, st);
@@ -385,8 +422,14 @@ GeomArgs geom_of(const hd_solver *s) {
   return g;
 }
 
+// Device E table: the phase-space E at the x-nodes, or for a constant field
+// the constant a_v at every x-node (read by the specialised kernel).
 hd_status upload_E(hd_solver *s) {
   const size_t n = (size_t)s->nE;
+  if (s->field_kind == 0) {
+    s->E_host.assign(n, 0.0);
+    for (size_t i = 0; i < n; ++i) s->E_host[i] = s->a_const[s->dx + (int)(i % (size_t)s->dx)];
+  }
   if (s->prec == HD_FP32) {
     std::vector<float> tmp(s->E_host.begin(), s->E_host.end());
     HD_HIP(hipMemcpy(s->E(), tmp.data(), n * sizeof(float), hipMemcpyHostToDevice));
@@ -501,8 +544,7 @@ hd_status hd_bind(hd_solver *s, void *ws, size_t bytes) {
   s->ws = reinterpret_cast<char *>(ws);
   s->cur = 0;
   HD_HIP(hipMemset(s->ws, 0, s->total));
-  if (s->field_kind == 1) return upload_E(s);
-  return HD_OK;
+  return upload_E(s);
 }
 
 hd_status hd_set_field_constant(hd_solver *s, const double *a) {
@@ -512,6 +554,7 @@ hd_status hd_set_field_constant(hd_solver *s, const double *a) {
   s->field_kind = 0;
   for (int j = 0; j < 6; ++j) s->a_const[j] = j < s->d ? a[j] : 0.0;
   drop_graphs(s);
+  if (s->ws) return upload_E(s);
   return HD_OK;
 }
 

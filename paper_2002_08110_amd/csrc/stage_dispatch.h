@@ -19,10 +19,11 @@ template <int D, int N, int DX, int RD, typename P, bool LDS>
 hipError_t launch_stage(const StageParams<P> &prm, const LaunchShape &ls, hipStream_t st) {
   auto fn = stage_kernel<D, N, DX, RD, P, LDS>;
   if (ls.shmem > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)ls.shmem);
-    if (e != hipSuccess) return e;
+    // Once per kernel: allow the largest LDS size any plan can request.
+    static const hipError_t attr = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+        (int)kMaxLdsBytes);
+    if (attr != hipSuccess) return attr;
   }
   hipLaunchKernelGGL(fn, dim3(ls.grid), dim3(ls.block), ls.shmem, st, prm);
   return hipGetLastError();
@@ -81,5 +82,10 @@ hipError_t stage_d3_f32(int n, int rd, int lds, const StageParams<float> &, cons
 hipError_t stage_d4_f32(int n, int rd, int lds, const StageParams<float> &, const LaunchShape &, hipStream_t);
 hipError_t stage_d5_f32(int n, int rd, int lds, const StageParams<float> &, const LaunchShape &, hipStream_t);
 hipError_t stage_d6_f32(int n, int rd, int lds, const StageParams<float> &, const LaunchShape &, hipStream_t);
+
+// Specialised kernel for d = 6 (3 x + 3 v), degree 3: one cell per
+// 256-thread workgroup (stage_k3.hip).
+hipError_t stage_k3_f64(const StageParams<double> &, unsigned grid, hipStream_t);
+hipError_t stage_k3_f32(const StageParams<float> &, unsigned grid, hipStream_t);
 
 }  // namespace hd

@@ -79,7 +79,17 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nblocks) {
 
 // Scheduling fence: keeps the compiler from hoisting the loads of later
 // dimensions above this point, which would multiply live registers.
-__device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
+// (An empty asm statement with a memory clobber: memory operations are not
+// moved across it, at the IR or the machine level.)
+__device__ __forceinline__ void sched_fence() {
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("" ::: "memory");
+}
+
+// Pin a value in a register at this point of the program: the computation
+// producing it cannot be sunk below (an empty asm that reads and writes it).
+__device__ __forceinline__ void pin(double &x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void pin(float &x) { asm volatile("" : "+v"(x)); }
 
 template <typename P>
 __device__ __forceinline__ P to_p(double v) {

@@ -72,11 +72,20 @@ def all_plans(case: W.Case, precision="fp64"):
         T = n ** (d - rd)
         for xcd in (0, 1):
             for wg in (64, 256):
-                plans.append(dict(lds=0, wg_size=wg, reg_dims=rd, xcd_remap=xcd, cells_per_wg=1))
+                plans.append(dict(lds=0, wg_size=wg, reg_dims=rd, xcd_remap=xcd, cells_per_wg=1,
+                                  kernel=0))
             if T <= 1024 and nd * psize <= 160 * 1024:
                 cpws = [1] if T > 256 else sorted({1, max(1, 256 // T)})
                 for cpw in cpws:
                     if cpw * nd * psize <= 160 * 1024:
                         plans.append(dict(lds=1, cells_per_wg=cpw, reg_dims=rd, xcd_remap=xcd,
-                                          wg_size=256))
+                                          wg_size=256, kernel=0))
+    if k3_eligible(case):
+        for xcd in (0, 1):
+            plans.append(dict(kernel=1, xcd_remap=xcd, reg_dims=2))
     return plans
+
+
+def k3_eligible(case: W.Case):
+    """The specialised kernel: 6D (3 x + 3 v), degree 3, < 2^31 DoFs."""
+    return case.dim_x == 3 and case.dim_v == 3 and case.degree == 3 and case.ndofs < 2 ** 31
