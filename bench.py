@@ -40,7 +40,63 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--precisions", default="fp64,fp32")
     ap.add_argument("--plan", default="", help="override plan, e.g. lds=1,reg_dims=1")
+    ap.add_argument("--mode", default="bench", choices=["bench", "stages", "copy"],
+                    help="stages: only run --steps x 5 stage launches per precision (for "
+                         "profilers); copy: a plain device copy of --copy-mib MiB (the "
+                         "calibration kernel for the byte counters)")
+    ap.add_argument("--copy-mib", type=int, default=4096)
     return ap.parse_args()
+
+
+def run_stages(case, precision, steps, plan_override):
+    """Only the fused stage launches (5 per step), for counter collection."""
+    import torch
+
+    from paper_2002_08110_amd.solver import Solver
+    S = Solver(case.dim_x, case.dim_v, case.cells, case.lo, case.hi, case.degree,
+               precision=precision)
+    if case.field == "sine":
+        S.set_field_sine(case.amp)
+    else:
+        S.set_field_constant(case.a)
+    if plan_override:
+        S.set_plan(**plan_override)
+    S.init_state(case.ic, list(case.ic_params))
+    dt = S.stable_dt(case.cfl)
+    for _ in range(steps):
+        for st in range(5):
+            S.rk_stage(st, dt)
+    torch.cuda.synchronize()
+    print("# ran %d stage launches (%s, plan %s)" % (5 * steps, precision, S.get_plan()),
+          file=sys.stderr, flush=True)
+    S.close()
+
+
+def run_copy(mib):
+    """The library's plain streaming copy (hd_stream_copy) of a known size,
+    three launches: the calibration kernel for the byte counters."""
+    import ctypes
+
+    import torch
+
+    from paper_2002_08110_amd import _hd
+    lib = _hd.load()
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(3):
+        _hd.check(lib.hd_stream_copy(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                                     n, stream))
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 3
+    print("# hd_stream_copy %d MiB: %.3f ms, %.0f GB/s (read + write)"
+          % (mib, ms, 2 * n * 8 / ms / 1e6), file=sys.stderr, flush=True)
 
 
 def measure(case, precision, steps, warmup, plan_override):
@@ -148,6 +204,13 @@ def main():
         for kv in args.plan.split(","):
             k, v = kv.split("=")
             plan[k] = int(v)
+    if args.mode == "copy":
+        run_copy(args.copy_mib)
+        return
+    if args.mode == "stages":
+        for prec in args.precisions.split(","):
+            run_stages(case, prec, args.steps, plan)
+        return
     results = {}
     for prec in args.precisions.split(","):
         results[prec] = measure(case, prec, args.steps, args.warmup, plan)

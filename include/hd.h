@@ -81,7 +81,12 @@ typedef struct hd_batch hd_batch;    /* opaque */
  *              registers (1 or 2; at most dim_v).
  *  kernel:     0 = the generic kernel (the fields above apply); 1 = the
  *              kernel specialised for d = 6 (3 x + 3 v) at degree 3, one cell
- *              per 256-thread workgroup (only xcd_remap applies). */
+ *              per 256-thread workgroup (only xcd_remap and options apply).
+ *  options:    bit 0: non-temporal (streaming) loads and stores of the stage
+ *              increment du and stores of the output solution, so they do
+ *              not displace cached neighbour data; bit 1 (kernel 1, FP32
+ *              only): keep the FP64 input solution in registers instead of
+ *              re-reading it for the update. */
 typedef struct {
   int lds;
   int cells_per_wg;
@@ -89,6 +94,7 @@ typedef struct {
   int xcd_remap;
   int reg_dims;
   int kernel;
+  int options;
 } hd_plan;
 
 /* Create a solver for `mesh` and polynomial degree `degree` (k+1 nodes per
@@ -167,6 +173,10 @@ hd_status hd_diagnostics(const hd_solver *s, double *mass, double *energy, hd_st
 /* Read / override the stage-kernel launch plan. */
 hd_status hd_get_plan(const hd_solver *s, hd_plan *plan);
 hd_status hd_set_plan(hd_solver *s, const hd_plan *plan);
+
+/* dst[i] = src[i], i < n, on the stream: a plain streaming copy used to
+ * measure achievable HBM bandwidth and to calibrate byte counters. */
+hd_status hd_stream_copy(const double *src, double *dst, size_t n, hd_stream stream);
 
 /* Message of the last error on this thread ("" if none). */
 const char *hd_last_error(void);

@@ -26,7 +26,7 @@ SYMBOLS = (
     "hd_set_state", "hd_init_state", "hd_state_ptr", "hd_get_state", "hd_apply",
     "hd_stable_dt", "hd_rk_stage", "hd_rk_step", "hd_diagnostics", "hd_get_plan",
     "hd_set_plan", "hd_last_error", "hd_batch_create", "hd_batch_destroy",
-    "hd_batch_step",
+    "hd_batch_step", "hd_stream_copy",
 )
 
 
@@ -39,7 +39,8 @@ class hd_mesh(ctypes.Structure):
 class hd_plan(ctypes.Structure):
     _fields_ = [("lds", ctypes.c_int), ("cells_per_wg", ctypes.c_int),
                 ("wg_size", ctypes.c_int), ("xcd_remap", ctypes.c_int),
-                ("reg_dims", ctypes.c_int), ("kernel", ctypes.c_int)]
+                ("reg_dims", ctypes.c_int), ("kernel", ctypes.c_int),
+                ("options", ctypes.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -92,6 +93,7 @@ def load():
         "hd_batch_create": ([P(vp), i, P(vp)], st),
         "hd_batch_destroy": ([vp], st),
         "hd_batch_step": ([vp, P(d), P(i), vp], st),
+        "hd_stream_copy": ([vp, vp, ctypes.c_size_t, vp], st),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

@@ -90,6 +90,10 @@ bool k3_eligible(const hd_solver *s) {
 }
 
 bool valid_plan(const hd_solver *s, const hd_plan &p, std::string *why) {
+  if (p.options < 0 || p.options > 3) {
+    *why = "options is a 2-bit mask";
+    return false;
+  }
   if (p.kernel != 0 && p.kernel != 1) {
     *why = "kernel must be 0 (generic) or 1 (6D degree-3)";
     return false;
@@ -152,6 +156,9 @@ hd_plan default_plan(const hd_solver *s) {
     p.cells_per_wg = 1;
   }
   p.kernel = k3_eligible(s) ? 1 : 0;
+  // Measured on MI355X (6D 8^6, k = 3): streaming du and the output solution
+  // helps both precisions, keeping the FP64 input in registers helps FP32.
+  p.options = p.kernel == 1 ? (s->prec == HD_FP32 ? 3 : 1) : 0;
   return p;
 }
 
@@ -221,7 +228,7 @@ hipError_t dispatch(const hd_solver *s, const hd::StageParams<P> &prm, const hd:
 template <>
 hipError_t dispatch<double>(const hd_solver *s, const hd::StageParams<double> &prm,
                             const hd::LaunchShape &ls, hipStream_t st) {
-  if (s->plan.kernel == 1) return hd::stage_k3_f64(prm, ls.grid, st);
+  if (s->plan.kernel == 1) return hd::stage_k3_f64(prm, ls.grid, s->plan.options, st);
   const int rd = s->plan.reg_dims, lds = s->plan.lds, n = s->n;
   switch (s->d) {
     case 2: return hd::stage_d2_f64(n, rd, lds, prm, ls, st);
@@ -236,7 +243,7 @@ hipError_t dispatch<double>(const hd_solver *s, const hd::StageParams<double> &p
 template <>
 hipError_t dispatch<float>(const hd_solver *s, const hd::StageParams<float> &prm,
                            const hd::LaunchShape &ls, hipStream_t st) {
-  if (s->plan.kernel == 1) return hd::stage_k3_f32(prm, ls.grid, st);
+  if (s->plan.kernel == 1) return hd::stage_k3_f32(prm, ls.grid, s->plan.options, st);
   const int rd = s->plan.reg_dims, lds = s->plan.lds, n = s->n;
   switch (s->d) {
     case 2: return hd::stage_d2_f32(n, rd, lds, prm, ls, st);
@@ -438,6 +445,19 @@ hd_status upload_E(hd_solver *s) {
   }
   drop_graphs(s);
   return HD_OK;
+}
+
+// Plain streaming copy, 16 bytes per lane per iteration.
+__global__ void __launch_bounds__(256) stream_copy_kernel(const double2 *__restrict__ src,
+                                                          double2 *__restrict__ dst, size_t n2) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride)
+    dst[i] = src[i];
+}
+
+__global__ void stream_copy_tail(const double *src, double *dst, size_t begin, size_t n) {
+  const size_t i = begin + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
 }
 
 }  // namespace
@@ -744,6 +764,26 @@ hd_status hd_diagnostics(const hd_solver *s, double *mass, double *energy, hd_st
   HD_HIP(hipStreamSynchronize(st));
   *mass = res[0];
   *energy = res[1];
+  return HD_OK;
+}
+
+hd_status hd_stream_copy(const double *src, double *dst, size_t n, hd_stream stream) {
+  if ((!src || !dst) && n) return fail(HD_ERR_INVALID, "NULL argument");
+  if (n == 0) return HD_OK;
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16)
+    return fail(HD_ERR_INVALID, "src and dst must be 16-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t n2 = n / 2;
+  if (n2) {
+    const unsigned blocks = (unsigned)std::min<size_t>((n2 + 255) / 256, 256 * 64);
+    hipLaunchKernelGGL(stream_copy_kernel, dim3(blocks), dim3(256), 0, st,
+                       reinterpret_cast<const double2 *>(src), reinterpret_cast<double2 *>(dst), n2);
+    HD_HIP(hipGetLastError());
+  }
+  if (n % 2) {
+    hipLaunchKernelGGL(stream_copy_tail, dim3(1), dim3(64), 0, st, src, dst, 2 * n2, n);
+    HD_HIP(hipGetLastError());
+  }
   return HD_OK;
 }
 

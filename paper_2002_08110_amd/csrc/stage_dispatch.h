@@ -85,7 +85,7 @@ hipError_t stage_d6_f32(int n, int rd, int lds, const StageParams<float> &, cons
 
 // Specialised kernel for d = 6 (3 x + 3 v), degree 3: one cell per
 // 256-thread workgroup (stage_k3.hip).
-hipError_t stage_k3_f64(const StageParams<double> &, unsigned grid, hipStream_t);
-hipError_t stage_k3_f32(const StageParams<float> &, unsigned grid, hipStream_t);
+hipError_t stage_k3_f64(const StageParams<double> &, unsigned grid, int options, hipStream_t);
+hipError_t stage_k3_f32(const StageParams<float> &, unsigned grid, int options, hipStream_t);
 
 }  // namespace hd

@@ -58,10 +58,29 @@ constexpr int k3_waves_per_eu() {
   return sizeof(P) == 8 ? 2 : 4;
 }
 
-template <typename P>
+// Plan options (hd_plan.options): bit 0 streams du and the output solution
+// with non-temporal accesses; bit 1 (FP32) keeps the FP64 input solution in
+// registers for the update instead of re-reading it.
+constexpr int kOptStream = 1;
+constexpr int kOptKeepU64 = 2;
+
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_opt(const T *p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st_opt(T *p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+template <typename P, int OPT>
 __global__ void __launch_bounds__(256)
     __attribute__((amdgpu_waves_per_eu(k3_waves_per_eu<P>(), k3_waves_per_eu<P>())))
     stage_k3_kernel(const StageParams<P> prm) {
+  constexpr bool NT = (OPT & kOptStream) != 0;
+  constexpr bool KEEPU = (OPT & kOptKeepU64) != 0 && sizeof(P) == 4;
   constexpr int N = 4, ND = kK3Nodes, F = kK3Face;
   extern __shared__ unsigned char smem_raw[];
   P *cellb = reinterpret_cast<P *>(smem_raw);
@@ -163,7 +182,7 @@ __global__ void __launch_bounds__(256)
   P dv[16];
   if (stage && prm.read_du) {
 #pragma unroll
-    for (int s = 0; s < 16; ++s) dv[s] = ducell[t + 256 * s];
+    for (int s = 0; s < 16; ++s) dv[s] = ld_opt<NT>(ducell + t + 256 * s);
   }
 
   // ---- phase C: sweeps ----
@@ -365,13 +384,16 @@ __global__ void __launch_bounds__(256)
   }
   if (prm.write_du) {
 #pragma unroll
-    for (int s = 0; s < 16; ++s) ducell[t + 256 * s] = dv[s];
+    for (int s = 0; s < 16; ++s) st_opt<NT>(ducell + t + 256 * s, dv[s]);
   }
   double *uocell = prm.u_out + (uint64_t)cell * ND;
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
-    const double uo = sizeof(P) == sizeof(double) ? (double)u[s] : ucell[t + 256 * s];
-    uocell[t + 256 * s] = uo + prm.rk_b * (double)dv[s];
+    double uo;
+    if constexpr (sizeof(P) == sizeof(double)) uo = (double)u[s];
+    else if constexpr (KEEPU) uo = ud[s];
+    else uo = ucell[t + 256 * s];
+    st_opt<NT>(uocell + t + 256 * s, uo + prm.rk_b * (double)dv[s]);
   }
 }
 

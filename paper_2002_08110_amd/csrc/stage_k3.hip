@@ -4,9 +4,9 @@
 
 namespace hd {
 
-template <typename P>
+template <typename P, int OPT>
 static hipError_t launch_k3(const StageParams<P> &prm, unsigned grid, hipStream_t st) {
-  auto fn = stage_k3_kernel<P>;
+  auto fn = stage_k3_kernel<P, OPT>;
   constexpr size_t shmem = k3_lds_bytes<P>();
   static const hipError_t attr = hipFuncSetAttribute(
       reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
@@ -15,11 +15,20 @@ static hipError_t launch_k3(const StageParams<P> &prm, unsigned grid, hipStream_
   return hipGetLastError();
 }
 
-hipError_t stage_k3_f64(const StageParams<double> &prm, unsigned grid, hipStream_t st) {
-  return launch_k3<double>(prm, grid, st);
+hipError_t stage_k3_f64(const StageParams<double> &prm, unsigned grid, int options,
+                        hipStream_t st) {
+  // bit 1 (keep the FP64 input) is implied in FP64
+  if (options & kOptStream) return launch_k3<double, kOptStream>(prm, grid, st);
+  return launch_k3<double, 0>(prm, grid, st);
 }
-hipError_t stage_k3_f32(const StageParams<float> &prm, unsigned grid, hipStream_t st) {
-  return launch_k3<float>(prm, grid, st);
+hipError_t stage_k3_f32(const StageParams<float> &prm, unsigned grid, int options,
+                        hipStream_t st) {
+  switch (options & 3) {
+    case 0: return launch_k3<float, 0>(prm, grid, st);
+    case 1: return launch_k3<float, 1>(prm, grid, st);
+    case 2: return launch_k3<float, 2>(prm, grid, st);
+    default: return launch_k3<float, 3>(prm, grid, st);
+  }
 }
 
 }  // namespace hd
