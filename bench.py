@@ -158,6 +158,26 @@ def measure(case, precision, steps, warmup, plan_override):
     return res
 
 
+def profiled_traffic(precision, plan_override):
+    """Bytes per stage launch from the committed byte-counter profile of the
+    default plan, or None if the kernel source changed since it was taken."""
+    if plan_override:
+        return None
+    from paper_2002_08110_amd import profiling
+    path = os.path.join(ROOT, "profiles", "stage_6d_8x6_k3_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    if data.get("kernel_source_digest") != profiling.kernel_source_digest():
+        return None
+    want = "stage_k3_kernel<double" if precision == "fp64" else "stage_k3_kernel<float"
+    for name, d in data["kernels"].items():
+        if want in name:
+            return d["bytes_per_launch"]
+    return None
+
+
 def cpu_baseline(case, seconds):
     """The oracle (zero-skipping mode, OpenMP over cells) on a bounded sample
     of cells of the same workload; throughput in DoF updates per second."""
@@ -238,7 +258,9 @@ def main():
                    "initial_state": "(1+0.01 cos(2 pi x1)) Maxwellian(v)",
                    "rk": "LSRK45 (5 fused stages per step)", "cfl": case.cfl},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": profiled_traffic(head["precision"], plan)
+                     if args.config == "6d" else None,
                      "kernel": "stage_kernel (fused LSRK stage)",
                      "algorithmic_bytes_per_dof": head["algorithmic_bytes_per_dof"]},
         "pct_hbm_peak": 100.0 * achieved / HBM_PEAK_GBPS,

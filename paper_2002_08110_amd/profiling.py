@@ -1,0 +1,126 @@
+"""Summaries of rocprofv3 output for the committed profiles.
+
+The byte counters FETCH_SIZE and WRITE_SIZE are taken in separate runs (one
+counter group per run). Each is scaled by what the same counter reports for
+the library's plain streaming copy (hd_stream_copy) of a known size, which
+reads and writes exactly that many bytes. The result is the bytes the fused
+stage kernel moves between L2 and memory per launch, written to a small JSON
+file that bench.py reports as roofline "traffic" while the kernel source is
+unchanged (checked with a digest of the kernel headers).
+
+Usage:
+  python -m paper_2002_08110_amd.profiling counters DIR COPY_MIB OUT_JSON OUT_MD
+  python -m paper_2002_08110_amd.profiling trace STATS_CSV COMMAND OUT_MD
+"""
+from __future__ import annotations
+
+import collections
+import csv
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ("csrc/stage_kernel.h", "csrc/stage_k3.h")
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _counter_means(path):
+    agg = collections.defaultdict(list)
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            agg[(r["Kernel_Name"], r["Counter_Name"])].append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in agg.items()}, {k: len(v) for k, v in agg.items()}
+
+
+def _pick(means, needle):
+    out = {}
+    for (k, c), v in means.items():
+        if needle in k:
+            out[k] = v
+    return out
+
+
+def counters(run_dir, copy_mib, out_json, out_md):
+    """run_dir holds fetch/, write/, cfetch/, cwrite/ rocprofv3 csv outputs."""
+    def csvp(name):
+        return os.path.join(run_dir, name, name + "_counter_collection.csv")
+
+    fetch, nf = _counter_means(csvp("fetch"))
+    write, nw = _counter_means(csvp("write"))
+    cfetch, _ = _counter_means(csvp("cfetch"))
+    cwrite, _ = _counter_means(csvp("cwrite"))
+    copy_kib = copy_mib * 1024.0
+    cf = list(_pick(cfetch, "stream_copy").values())[0]
+    cw = list(_pick(cwrite, "stream_copy").values())[0]
+    f_scale = copy_kib / cf
+    w_scale = copy_kib / cw
+    res = {"kernel_source_digest": kernel_source_digest(), "copy_mib": copy_mib,
+           "copy_fetch_kib": cf, "copy_write_kib": cw,
+           "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
+    for (k, c), v in fetch.items():
+        if "stage" not in k:
+            continue
+        wv = write.get((k, "WRITE_SIZE"))
+        res["kernels"][k] = {
+            "launches": nf[(k, c)], "fetch_kib": v, "write_kib": wv,
+            "bytes_per_launch": (v * f_scale + wv * w_scale) * 1024.0,
+        }
+    with open(out_json, "w") as f:
+        json.dump(res, f, indent=1)
+    lines = ["# Byte counters of the fused stage kernels", "",
+             "Counters per dispatch (KiB, mean over the dispatches of two RK steps of",
+             "the 6D 8^6 k=3 workload), scaled by the library's plain copy of %d MiB:" % copy_mib,
+             "", "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | bytes/launch (scaled) |",
+             "|---|---|---|---|---|"]
+    for k, d in res["kernels"].items():
+        lines.append("| `%s` | %d | %.4g | %.4g | %.4g GB |" % (k, d["launches"], d["fetch_kib"],
+                                                                d["write_kib"],
+                                                                d["bytes_per_launch"] / 1e9))
+    lines += ["", "Commands (one counter per run, from the repository root after",
+              "`cd /tmp && export TMPDIR=/tmp`):", "", "```"]
+    for name, cnt, mode in (("fetch", "FETCH_SIZE", "--mode stages --steps 2"),
+                            ("write", "WRITE_SIZE", "--mode stages --steps 2"),
+                            ("cfetch", "FETCH_SIZE", "--mode copy --copy-mib %d" % copy_mib),
+                            ("cwrite", "WRITE_SIZE", "--mode copy --copy-mib %d" % copy_mib)):
+        lines.append("rocprofv3 --pmc %s --output-format csv -d gpurun_out/prof/%s -o %s -- "
+                     "python3 bench.py %s" % (cnt, name, name, mode))
+    lines += ["python -m paper_2002_08110_amd.profiling counters gpurun_out/prof %d "
+              "profiles/<name>_traffic.json profiles/<name>_counters.md" % copy_mib, "```"]
+    lines += ["", "Copy calibration: FETCH_SIZE %.4g KiB and WRITE_SIZE %.4g KiB for %d MiB "
+              "read + %d MiB written: scales %.3f (fetch) and %.3f (write)."
+              % (cf, cw, copy_mib, copy_mib, f_scale, w_scale),
+              "", "Kernel source digest: `%s`." % res["kernel_source_digest"]]
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return res
+
+
+def trace(stats_csv, command, out_md):
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = ["# Kernel trace summary", "", "Command:", "", "```", command, "```", "",
+             "| kernel | calls | average ms | min ms | max ms | share % |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append("| `%s` | %s | %.4f | %.4f | %.4f | %.2f |" % (
+            r["Name"][:90], r["Calls"], float(r["AverageNs"]) / 1e6, float(r["MinNs"]) / 1e6,
+            float(r["MaxNs"]) / 1e6, float(r["Percentage"])))
+    lines += ["", "Kernel source digest: `%s`." % kernel_source_digest()]
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "counters":
+        counters(sys.argv[2], int(sys.argv[3]), sys.argv[4], sys.argv[5])
+    elif sys.argv[1] == "trace":
+        trace(sys.argv[2], sys.argv[3], sys.argv[4])
+    else:
+        raise SystemExit(__doc__)
