@@ -12,12 +12,12 @@
 #include <string>
 #include <vector>
 
-#include "gl_tables.h"
-#include "hd.h"
+#include "hd_internal.h"
 #include "stage_dispatch.h"
 #include "stage_k3.h"
 
-namespace {
+namespace hd {
+namespace rt {
 
 thread_local std::string g_err;
 
@@ -25,19 +25,6 @@ hd_status fail(hd_status st, const std::string &msg) {
   g_err = msg;
   return st;
 }
-
-#define HD_HIP(expr)                                                                    \
-  do {                                                                                  \
-    hipError_t e_ = (expr);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      return fail(HD_ERR_HIP, std::string(#expr) + " failed: " + hipGetErrorString(e_)); \
-  } while (0)
-
-constexpr size_t kAlign = 256;
-constexpr int kDiagBlocks = 1024;
-constexpr int kDiagThreads = 256;
-
-size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Carpenter & Kennedy (1994) five-stage fourth-order 2N-storage scheme,
 // the low-storage RK scheme of Sec. 5.4 (order 4, 5 stages, 3 vectors).
@@ -49,45 +36,28 @@ const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 136
                         1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
                         2277821191437.0 / 14882151754819.0};
 
-}  // namespace
-
-struct hd_solver {
-  hd_mesh mesh{};
-  int d = 0, dx = 0, dv = 0, k = 0, n = 0, prec = 0;
-  int64_t nd = 0, ncells = 0, ndofs = 0;
-  double h[6] = {0};
-  hd::Tables1D tab;
-  int field_kind = 0;
-  double a_const[6] = {0};
-  double esign = 1.0;
-  std::vector<double> E_host;  // E at x-nodes (phase-space field)
-  int64_t nE = 0;              // entries of the E table
-  // Workspace layout (offsets into the caller's buffer).
-  size_t off_u[2] = {0, 0}, off_du = 0, off_E = 0, off_part = 0, total = 0;
-  char *ws = nullptr;
-  int cur = 0;  // which of the two solution buffers holds the solution
-  hd_plan plan{};
-  // Captured RK steps (index = solution buffer parity at the start).
-  hipStream_t cap = nullptr;
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
-  double gdt = 0.0;
-  bool gvalid = false;
-
-  double *u(int i) const { return reinterpret_cast<double *>(ws + off_u[i]); }
-  void *du() const { return ws + off_du; }
-  void *E() const { return ws + off_E; }
-  double *part() const { return reinterpret_cast<double *>(ws + off_part); }
-  size_t psize() const { return prec == HD_FP32 ? sizeof(float) : sizeof(double); }
-};
-
+}  // namespace rt
+}  // namespace hd
 
 namespace {
 
-// The specialised kernel covers d = 6 (3 x + 3 v) at degree 3.
-// Its in-kernel neighbour offsets are 32-bit DoF counts: fewer than 2^31 DoFs.
-bool k3_eligible(const hd_solver *s) {
-  return s->d == 6 && s->dx == 3 && s->n == 4 && s->ndofs < (int64_t(1) << 31);
-}
+using hd::rt::fail;
+using hd::rt::fill_params;
+using hd::rt::k3_eligible;
+using hd::rt::kRkA;
+using hd::rt::kRkB;
+
+constexpr size_t kAlign = 256;
+constexpr int kDiagBlocks = 1024;
+constexpr int kDiagThreads = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+}  // namespace
+
+
+
+namespace {
 
 bool valid_plan(const hd_solver *s, const hd_plan &p, std::string *why) {
   if (p.options < 0 || p.options > 3) {
@@ -162,41 +132,6 @@ hd_plan default_plan(const hd_solver *s) {
   return p;
 }
 
-template <typename P>
-void fill_params(const hd_solver *s, hd::StageParams<P> *prm) {
-  std::memset(prm, 0, sizeof(*prm));
-  prm->ncells = (unsigned)s->ncells;
-  unsigned st = 1;
-  for (int j = 0; j < s->d; ++j) {
-    prm->cells[j] = (unsigned)s->mesh.cells[j];
-    prm->cstride[j] = st;
-    st *= (unsigned)s->mesh.cells[j];
-    prm->inv_h[j] = (P)(1.0 / s->h[j]);
-    // lift = 1 / w_0 = 1 / w_k (boundary Gauss-Lobatto weight on [0,1]).
-    prm->lift_inv_h[j] = (P)(1.0 / (s->tab.w[0] * s->h[j]));
-    prm->a_const[j] = (P)s->a_const[j];
-    prm->vlo[j] = (P)s->mesh.lo[j];
-    prm->vh[j] = (P)s->h[j];
-  }
-  for (int m = 0; m < s->n; ++m) prm->xi[m] = (P)s->tab.xi[m];
-  for (int q = 0; q < s->n * s->n; ++q) prm->Dm[q] = (P)s->tab.D[q];
-  prm->field_kind = s->field_kind;
-  prm->esign = (P)s->esign;
-  prm->E = reinterpret_cast<const P *>(s->E());
-  prm->xcd_remap = s->plan.xcd_remap;
-  prm->cells_per_wg = (unsigned)s->plan.cells_per_wg;
-  if (s->plan.kernel == 1 && s->field_kind == 0) {
-    // The specialised kernel reads every field in phase-space form: the
-    // constant a_x as a velocity coordinate with zero cell width, the
-    // constant a_v from the E table (filled with the constants).
-    for (int j = 0; j < s->dx; ++j) {
-      prm->vlo[s->dx + j] = (P)s->a_const[j];
-      prm->vh[s->dx + j] = P(0);
-    }
-    prm->esign = P(1);
-  }
-}
-
 hd::LaunchShape shape_of(const hd_solver *s) {
   hd::LaunchShape ls{};
   if (s->plan.kernel == 1) {
@@ -266,7 +201,7 @@ template <typename P>
 hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, int mode,
                     int stage, double dt, hipStream_t st) {
   hd::StageParams<P> prm;
-  fill_params<P>(s, &prm);
+  fill_params<P>(s, &prm, s->plan.kernel);
   const hd::LaunchShape ls = shape_of(s);
   prm.nblocks = ls.grid;
   prm.u_in = in;
@@ -468,7 +403,7 @@ __global__ void stream_copy_tail(const double *src, double *dst, size_t begin, s
 
 extern "C" {
 
-const char *hd_last_error(void) { return g_err.c_str(); }
+const char *hd_last_error(void) { return hd::rt::g_err.c_str(); }
 
 hd_status hd_create(const hd_mesh *mesh, int degree, int prec, hd_solver **out) {
   if (!mesh || !out) return fail(HD_ERR_INVALID, "NULL argument");

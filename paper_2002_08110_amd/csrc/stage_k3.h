@@ -75,19 +75,16 @@ __device__ __forceinline__ void st_opt(T *p, T v) {
   else *p = v;
 }
 
+// One workgroup's cell `cell` (the kernel below and the batched persistent
+// kernel call it; lds_reuse as in stage_body).
 template <typename P, int OPT>
-__global__ void __launch_bounds__(256)
-    __attribute__((amdgpu_waves_per_eu(k3_waves_per_eu<P>(), k3_waves_per_eu<P>())))
-    stage_k3_kernel(const StageParams<P> prm) {
+__device__ __forceinline__ void stage_k3_body(const StageParams<P> &prm, unsigned cell,
+                                              unsigned char *smem_raw, bool lds_reuse) {
   constexpr bool NT = (OPT & kOptStream) != 0;
   constexpr bool KEEPU = (OPT & kOptKeepU64) != 0 && sizeof(P) == 4;
   constexpr int N = 4, ND = kK3Nodes, F = kK3Face;
-  extern __shared__ unsigned char smem_raw[];
   P *cellb = reinterpret_cast<P *>(smem_raw);
   P *faceb = cellb + ND;
-
-  unsigned cell = blockIdx.x;
-  if (prm.xcd_remap) cell = xcd_tile(cell, prm.nblocks);
   const int t = threadIdx.x;
   const int l = t & 63;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -166,6 +163,7 @@ __global__ void __launch_bounds__(256)
   }
   sched_fence();
   // ---- phase B: stage the cell and the layers in LDS ----
+  if (lds_reuse) __syncthreads();
   P u[16];
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
@@ -395,6 +393,16 @@ __global__ void __launch_bounds__(256)
     else uo = ucell[t + 256 * s];
     st_opt<NT>(uocell + t + 256 * s, uo + prm.rk_b * (double)dv[s]);
   }
+}
+
+template <typename P, int OPT>
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(k3_waves_per_eu<P>(), k3_waves_per_eu<P>())))
+    stage_k3_kernel(const StageParams<P> prm) {
+  extern __shared__ unsigned char smem_raw[];
+  unsigned cell = blockIdx.x;
+  if (prm.xcd_remap) cell = xcd_tile(cell, prm.nblocks);
+  stage_k3_body<P, OPT>(prm, cell, smem_raw, false);
 }
 
 #undef Dm

@@ -103,9 +103,13 @@ constexpr int stage_max_threads() {
   return (USE_LDS && ipow(N, D - RD) > 256) ? 1024 : 256;
 }
 
+// One workgroup's share of a stage: the cell tile `tile`. Called by the
+// stage kernel below and by the batched persistent kernel, which loops over
+// tiles of several solves (lds_reuse: the LDS of a previous tile may still be
+// read by other threads, so wait before overwriting it).
 template <int D, int N, int DX, int RD, typename P, bool USE_LDS>
-__global__ void __launch_bounds__((stage_max_threads<D, N, RD, USE_LDS>()))
-    stage_kernel(const StageParams<P> prm) {
+__device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned tile, P *lds,
+                                           bool lds_reuse) {
   constexpr int DV = D - DX;
   static_assert(RD >= 1 && RD <= DV, "register dims must be velocity dims");
   constexpr int NF = D - RD;          // thread-distributed (fast) dims
@@ -114,11 +118,6 @@ __global__ void __launch_bounds__((stage_max_threads<D, N, RD, USE_LDS>()))
   constexpr int NS = ipow(N, RD);     // nodes per thread
   static_assert(DX <= NF, "all x dims are thread-distributed");
 
-  extern __shared__ unsigned char smem_raw[];
-  P *lds = reinterpret_cast<P *>(smem_raw);
-
-  unsigned tile = blockIdx.x;
-  if (prm.xcd_remap) tile = xcd_tile(tile, prm.nblocks);
   unsigned cell, f, lc = 0;
   if constexpr (USE_LDS) {
     lc = threadIdx.x / T;
@@ -129,7 +128,9 @@ __global__ void __launch_bounds__((stage_max_threads<D, N, RD, USE_LDS>()))
     cell = (unsigned)(p / T);
     f = (unsigned)(p - (uint64_t)cell * T);
   }
-  const bool active = cell < prm.ncells;
+  // (A workgroup wider than cells_per_wg * T - the batched kernel's fixed
+  // 256 threads - leaves the extra threads inactive.)
+  const bool active = cell < prm.ncells && (!USE_LDS || lc < prm.cells_per_wg);
   if constexpr (!USE_LDS) {
     if (!active) return;
   }
@@ -156,8 +157,11 @@ __global__ void __launch_bounds__((stage_max_threads<D, N, RD, USE_LDS>()))
   for (int s = 0; s < NS; ++s) u[s] = to_p<P>(prm.u_in[base + (uint64_t)s * T]);
   const bool stage = prm.mode == 1;
   if constexpr (USE_LDS) {
+    if (lds_reuse) __syncthreads();
+    if (active) {
 #pragma unroll
-    for (int s = 0; s < NS; ++s) lds[lc * ND + f + s * T] = u[s];
+      for (int s = 0; s < NS; ++s) lds[lc * ND + f + s * T] = u[s];
+    }
     __syncthreads();
     if (!active) return;
   }
@@ -350,6 +354,15 @@ __global__ void __launch_bounds__((stage_max_threads<D, N, RD, USE_LDS>()))
     const double uo = sizeof(P) == sizeof(double) ? (double)u[s] : prm.u_in[base + (uint64_t)s * T];
     prm.u_out[base + (uint64_t)s * T] = uo + prm.rk_b * (double)dv[s];
   }
+}
+
+template <int D, int N, int DX, int RD, typename P, bool USE_LDS>
+__global__ void __launch_bounds__((stage_max_threads<D, N, RD, USE_LDS>()))
+    stage_kernel(const StageParams<P> prm) {
+  extern __shared__ unsigned char smem_raw[];
+  unsigned tile = blockIdx.x;
+  if (prm.xcd_remap) tile = xcd_tile(tile, prm.nblocks);
+  stage_body<D, N, DX, RD, P, USE_LDS>(prm, tile, reinterpret_cast<P *>(smem_raw), false);
 }
 
 }  // namespace hd

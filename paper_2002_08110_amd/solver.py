@@ -168,3 +168,48 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """hd_batch over bound Solvers of one precision: one persistent launch per
+    RK stage for all active solves, one hipGraph replay per step."""
+
+    def __init__(self, solvers):
+        self.lib = _hd.load()
+        self.solvers = list(solvers)
+        arr = (ctypes.c_void_p * len(self.solvers))(*[s.h.value for s in self.solvers])
+        h = ctypes.c_void_p()
+        check(self.lib.hd_batch_create(arr, len(self.solvers), ctypes.byref(h)))
+        self.h = h
+
+    def step(self, dts, active=None, stream=None):
+        n = len(self.solvers)
+        dt = (ctypes.c_double * n)(*[float(x) for x in dts])
+        act = None if active is None else (ctypes.c_int * n)(*[int(bool(a)) for a in active])
+        check(self.lib.hd_batch_step(self.h, dt, act, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.hd_batch_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_plan(d, k, dim_v, precision):
+    """The launch plan the batched kernel uses for a (d, k, precision) solve;
+    a single Solver set to this plan computes bitwise the same stage."""
+    n = k + 1
+    psize = 4 if precision == "fp32" else 8
+    if d == 6 and k == 3:
+        return dict(kernel=1, options=3 if precision == "fp32" else 1, reg_dims=2, lds=1,
+                    cells_per_wg=1, wg_size=256, xcd_remap=0)
+    rd = 2 if (n <= 3 and dim_v >= 2) else 1
+    T = n ** (d - rd)
+    lds = T <= 256 and (256 // T) * n ** d * psize <= 40 * 1024
+    return dict(kernel=0, options=0, reg_dims=rd, lds=int(lds), cells_per_wg=256 // T if lds else 1,
+                wg_size=256, xcd_remap=0)
