@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--precisions", default="fp64,fp32")
     ap.add_argument("--plan", default="", help="override plan, e.g. lds=1,reg_dims=1")
-    ap.add_argument("--mode", default="bench", choices=["bench", "stages", "copy"],
+    ap.add_argument("--mode", default="bench", choices=["bench", "stages", "copy", "batch"],
                     help="stages: only run --steps x 5 stage launches per precision (for "
                          "profilers); copy: a plain device copy of --copy-mib MiB (the "
                          "calibration kernel for the byte counters)")
@@ -158,6 +158,67 @@ def measure(case, precision, steps, warmup, plan_override):
     return res
 
 
+def _make_solver(case, precision):
+    from paper_2002_08110_amd.solver import Solver
+    S = Solver(case.dim_x, case.dim_v, case.cells, case.lo, case.hi, case.degree,
+               precision=precision)
+    if case.field == "sine":
+        S.set_field_sine(case.amp)
+    else:
+        S.set_field_constant(case.a)
+    S.init_state(case.ic, list(case.ic_params))
+    return S
+
+
+def run_batch(steps, seq_steps):
+    """The seeded mix of 96 uneven solves (6D and lower, degrees 2-5) advanced
+    together: one persistent launch per RK stage, one hipGraph per step, FP32
+    operator mode. Compared with the same solves stepped one after another
+    (FP32, then FP64). Prints one JSON line."""
+    import torch
+
+    from paper_2002_08110_amd import workloads as W
+    from paper_2002_08110_amd.solver import Batch
+    cases = W.batch_mix()
+    total = sum(c.ndofs for c in cases)
+    res = {"metric": "batched DoF-updates/s per RK stage (96-solve mix)", "unit": "DoF-updates/s",
+           "solves": len(cases), "total_dofs": total, "steps": steps}
+
+    def timed(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3
+
+    solvers = [_make_solver(c, "fp32") for c in cases]
+    dts = [S.stable_dt(c.cfl) for S, c in zip(solvers, cases)]
+    B = Batch(solvers)
+    B.step(dts)
+    t = timed(lambda: [B.step(dts) for _ in range(steps)])
+    res["value"] = total * 5 * steps / t
+    res["batched_fp32_s"] = t
+    t_seq = timed(lambda: [S.rk_step(dt, seq_steps) for S, dt in zip(solvers, dts)])
+    res["sequential_fp32"] = total * 5 * seq_steps / t_seq
+    B.close()
+    del B, solvers
+    torch.cuda.empty_cache()
+    solvers = [_make_solver(c, "fp64") for c in cases]
+    for S, dt in zip(solvers, dts):
+        S.rk_step(dt, 1)
+    t64 = timed(lambda: [S.rk_step(dt, seq_steps) for S, dt in zip(solvers, dts)])
+    res["sequential_fp64"] = total * 5 * seq_steps / t64
+    del solvers
+    torch.cuda.empty_cache()
+    print("# batch %.3e, sequential fp32 %.3e, sequential fp64 %.3e DoF-updates/s per stage"
+          % (res["value"], res["sequential_fp32"], res["sequential_fp64"]), file=sys.stderr,
+          flush=True)
+    print(json.dumps(res), flush=True)
+
+
 def profiled_traffic(precision, plan_override):
     """Bytes per stage launch from the committed byte-counter profile of the
     default plan, or None if the kernel source changed since it was taken."""
@@ -226,6 +287,9 @@ def main():
             plan[k] = int(v)
     if args.mode == "copy":
         run_copy(args.copy_mib)
+        return
+    if args.mode == "batch":
+        run_batch(args.steps, max(1, args.steps // 5))
         return
     if args.mode == "stages":
         for prec in args.precisions.split(","):

@@ -91,7 +91,9 @@ def batch_mix(seed=2002, count=96, dims=(3, 4, 5, 6), degrees=(2, 3, 4, 5),
               dof_range=(1e6, 2e8), cells_range=(4, 16), d3_cells_max=40,
               steps=50, max_tries=1000):
     """96 seeded solves of uneven dimension, degree and size. d = 3 cannot
-    reach 1M DoFs with <= 16 cells per dim, so its range extends to 40."""
+    reach 1M DoFs with <= 16 cells per dim, so its range extends to 40. Even
+    solves get a constant field, odd ones the phase-space field where the
+    split allows it (d_x = d_v), a constant field otherwise."""
     rng = np.random.default_rng(seed)
     cases = []
     for i in range(count):
@@ -105,7 +107,8 @@ def batch_mix(seed=2002, count=96, dims=(3, 4, 5, 6), degrees=(2, 3, 4, 5),
             if dof_range[0] <= nd <= dof_range[1]:
                 break
         dx, dv = SPLITS[d]
-        if i % 2 == 0:
+        # Odd d (2+1, 3+2) has no phase-space field a = (v, E(x)): constant there.
+        if i % 2 == 0 or dx != dv:
             a = list(rng.uniform(-1, 1, d))
             cases.append(Case("batch%02d" % i, dx, dv, cells, [0.0] * d, [1.0] * d, k,
                               "constant", a=a, ic=0, steps=steps))
@@ -140,7 +143,7 @@ def serve_trace(seed=811, count=2000, rate=20.0, dims=(4, 5, 6), degrees=(2, 3, 
                 break
         nsteps = int(rng.integers(steps[0], steps[1] + 1))
         dx, dv = SPLITS[d]
-        if i % 2 == 0:
+        if i % 2 == 0 or dx != dv:
             case = Case("req%04d" % i, dx, dv, cells, [0.0] * d, [1.0] * d, k, "constant",
                         a=list(rng.uniform(-1, 1, d)), ic=0, steps=nsteps)
         else:
