@@ -11,6 +11,7 @@
 
 #include "gl_tables.h"
 #include "hd.h"
+#include "stage_dispatch.h"
 #include "stage_kernel.h"
 
 struct hd_solver {
@@ -34,6 +35,7 @@ struct hd_solver {
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   double gdt = 0.0;
   bool gvalid = false;
+  uint64_t version = 0;  // bumped when the plan, field or memory changes
 
   double *u(int i) const { return reinterpret_cast<double *>(ws + off_u[i]); }
   void *du() const { return ws + off_du; }
@@ -63,6 +65,18 @@ inline bool k3_eligible(const hd_solver *s) {
   return s->d == 6 && s->dx == 3 && s->n == 4 && s->ndofs < (int64_t(1) << 31);
 }
 
+// Grid, workgroup size and dynamic LDS of one stage launch under the
+// solver's plan.
+hd::LaunchShape shape_of(const hd_solver *s);
+
+// Entry of the compiled stage kernel of the solver's plan; nullptr if none
+// is compiled.
+const void *stage_entry(const hd_solver *s);
+
+// Enqueue the five fused stages of one RK step of s on st, starting from
+// solution buffer `par` (the solution ends in buffer 1 - par). s->cur is
+// not changed.
+hd_status enqueue_step(hd_solver *s, int par, double dt, hipStream_t st);
 
 // Kernel parameters of a solver (everything but the per-launch fields:
 // buffers, mode, RK coefficients, dt). kernel = 1 passes constant fields in

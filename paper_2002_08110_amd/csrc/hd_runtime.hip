@@ -132,7 +132,9 @@ hd_plan default_plan(const hd_solver *s) {
   return p;
 }
 
-hd::LaunchShape shape_of(const hd_solver *s) {
+}  // namespace
+
+hd::LaunchShape hd::rt::shape_of(const hd_solver *s) {
   hd::LaunchShape ls{};
   if (s->plan.kernel == 1) {
     ls.grid = (unsigned)s->ncells;
@@ -156,39 +158,28 @@ hd::LaunchShape shape_of(const hd_solver *s) {
   return ls;
 }
 
-template <typename P>
-hipError_t dispatch(const hd_solver *s, const hd::StageParams<P> &prm, const hd::LaunchShape &ls,
-                    hipStream_t st);
+namespace hd {
+namespace rt {
 
-template <>
-hipError_t dispatch<double>(const hd_solver *s, const hd::StageParams<double> &prm,
-                            const hd::LaunchShape &ls, hipStream_t st) {
-  if (s->plan.kernel == 1) return hd::stage_k3_f64(prm, ls.grid, s->plan.options, st);
+const void *stage_entry(const hd_solver *s) {
+  const bool f32 = s->prec == HD_FP32;
+  if (s->plan.kernel == 1) return f32 ? hd::stage_k3_f32(s->plan.options)
+                                      : hd::stage_k3_f64(s->plan.options);
   const int rd = s->plan.reg_dims, lds = s->plan.lds, n = s->n;
   switch (s->d) {
-    case 2: return hd::stage_d2_f64(n, rd, lds, prm, ls, st);
-    case 3: return hd::stage_d3_f64(n, rd, lds, prm, ls, st);
-    case 4: return hd::stage_d4_f64(n, rd, lds, prm, ls, st);
-    case 5: return hd::stage_d5_f64(n, rd, lds, prm, ls, st);
-    case 6: return hd::stage_d6_f64(n, rd, lds, prm, ls, st);
+    case 2: return f32 ? hd::stage_d2_f32(n, rd, lds) : hd::stage_d2_f64(n, rd, lds);
+    case 3: return f32 ? hd::stage_d3_f32(n, rd, lds) : hd::stage_d3_f64(n, rd, lds);
+    case 4: return f32 ? hd::stage_d4_f32(n, rd, lds) : hd::stage_d4_f64(n, rd, lds);
+    case 5: return f32 ? hd::stage_d5_f32(n, rd, lds) : hd::stage_d5_f64(n, rd, lds);
+    case 6: return f32 ? hd::stage_d6_f32(n, rd, lds) : hd::stage_d6_f64(n, rd, lds);
   }
-  return hipErrorInvalidConfiguration;
+  return nullptr;
 }
 
-template <>
-hipError_t dispatch<float>(const hd_solver *s, const hd::StageParams<float> &prm,
-                           const hd::LaunchShape &ls, hipStream_t st) {
-  if (s->plan.kernel == 1) return hd::stage_k3_f32(prm, ls.grid, s->plan.options, st);
-  const int rd = s->plan.reg_dims, lds = s->plan.lds, n = s->n;
-  switch (s->d) {
-    case 2: return hd::stage_d2_f32(n, rd, lds, prm, ls, st);
-    case 3: return hd::stage_d3_f32(n, rd, lds, prm, ls, st);
-    case 4: return hd::stage_d4_f32(n, rd, lds, prm, ls, st);
-    case 5: return hd::stage_d5_f32(n, rd, lds, prm, ls, st);
-    case 6: return hd::stage_d6_f32(n, rd, lds, prm, ls, st);
-  }
-  return hipErrorInvalidConfiguration;
-}
+}  // namespace rt
+}  // namespace hd
+
+namespace {
 
 // Supported field/mesh combinations for the split x/v dimensions: the d = 2..6
 // splits 1+1, 2+1, 2+2, 3+2, 3+3 are compiled.
@@ -202,7 +193,7 @@ hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, in
                     int stage, double dt, hipStream_t st) {
   hd::StageParams<P> prm;
   fill_params<P>(s, &prm, s->plan.kernel);
-  const hd::LaunchShape ls = shape_of(s);
+  const hd::LaunchShape ls = hd::rt::shape_of(s);
   prm.nblocks = ls.grid;
   prm.u_in = in;
   prm.mode = mode;
@@ -218,7 +209,10 @@ hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, in
     prm.dt = (P)dt;
   }
   if (ls.grid == 0) return HD_OK;
-  hipError_t e = dispatch<P>(s, prm, ls, st);
+  const void *fn = hd::rt::stage_entry(s);
+  if (!fn) return fail(HD_ERR_HIP, "no compiled stage kernel for this plan");
+  void *args[] = {&prm};
+  hipError_t e = hipLaunchKernel(fn, dim3(ls.grid), dim3(ls.block), args, ls.shmem, st);
   if (e != hipSuccess) return fail(HD_ERR_HIP, std::string("stage kernel launch: ") + hipGetErrorString(e));
   return HD_OK;
 }
@@ -239,6 +233,12 @@ void drop_graphs(hd_solver *s) {
       s->gexec[i] = nullptr;
     }
   s->gvalid = false;
+}
+
+// The solver's plan, field or memory changed: captured steps are stale.
+void changed(hd_solver *s) {
+  drop_graphs(s);
+  ++s->version;
 }
 
 hd_status check_bound(const hd_solver *s) {
@@ -378,7 +378,7 @@ hd_status upload_E(hd_solver *s) {
   } else {
     HD_HIP(hipMemcpy(s->E(), s->E_host.data(), n * sizeof(double), hipMemcpyHostToDevice));
   }
-  drop_graphs(s);
+  changed(s);
   return HD_OK;
 }
 
@@ -400,6 +400,16 @@ __global__ void stream_copy_tail(const double *src, double *dst, size_t begin, s
 // ===========================================================================
 // ABI
 // ===========================================================================
+
+hd_status hd::rt::enqueue_step(hd_solver *s, int par, double dt, hipStream_t st) {
+  for (int stage = 0; stage < 5; ++stage, par = 1 - par) {
+    const hd_status r =
+        s->prec == HD_FP32 ? launch_op<float>(s, s->u(par), nullptr, s->u(1 - par), 1, stage, dt, st)
+                           : launch_op<double>(s, s->u(par), nullptr, s->u(1 - par), 1, stage, dt, st);
+    if (r != HD_OK) return r;
+  }
+  return HD_OK;
+}
 
 extern "C" {
 
@@ -495,7 +505,7 @@ hd_status hd_bind(hd_solver *s, void *ws, size_t bytes) {
   if (bytes < s->total) return fail(HD_ERR_INVALID, "workspace smaller than hd_required_bytes");
   if (reinterpret_cast<uintptr_t>(ws) % kAlign)
     return fail(HD_ERR_INVALID, "workspace must be 256-byte aligned");
-  drop_graphs(s);
+  changed(s);
   s->ws = reinterpret_cast<char *>(ws);
   s->cur = 0;
   HD_HIP(hipMemset(s->ws, 0, s->total));
@@ -508,7 +518,7 @@ hd_status hd_set_field_constant(hd_solver *s, const double *a) {
     if (!std::isfinite(a[j])) return fail(HD_ERR_INVALID, "field must be finite");
   s->field_kind = 0;
   for (int j = 0; j < 6; ++j) s->a_const[j] = j < s->d ? a[j] : 0.0;
-  drop_graphs(s);
+  changed(s);
   if (s->ws) return upload_E(s);
   return HD_OK;
 }
@@ -733,7 +743,7 @@ hd_status hd_set_plan(hd_solver *s, const hd_plan *plan) {
   std::string why;
   if (!valid_plan(s, *plan, &why)) return fail(HD_ERR_INVALID, why);
   s->plan = *plan;
-  drop_graphs(s);
+  changed(s);
   return HD_OK;
 }
 

@@ -2,8 +2,7 @@
 #include "stage_dispatch.h"
 
 namespace hd {
-hipError_t stage_d2_f64(int n, int rd, int lds, const StageParams<double> &prm,
-                         const LaunchShape &ls, hipStream_t st) {
-  return dispatch_n<2, 1, double>(n, rd, lds, prm, ls, st);
+const void *stage_d2_f64(int n, int rd, int lds) {
+  return resolve_n<2, 1, double>(n, rd, lds);
 }
 }  // namespace hd

@@ -1,33 +1,27 @@
-// Launchers of the specialised six-dimensional degree-3 stage kernel.
+// Entries of the specialised six-dimensional degree-3 stage kernel.
 #include "stage_dispatch.h"
 #include "stage_k3.h"
 
 namespace hd {
 
 template <typename P, int OPT>
-static hipError_t launch_k3(const StageParams<P> &prm, unsigned grid, hipStream_t st) {
-  auto fn = stage_k3_kernel<P, OPT>;
-  constexpr size_t shmem = k3_lds_bytes<P>();
-  static const hipError_t attr = hipFuncSetAttribute(
-      reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-  if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(256), shmem, st, prm);
-  return hipGetLastError();
+static const void *k3_fn() {
+  static const void *const f =
+      allow_max_lds(reinterpret_cast<const void *>(&stage_k3_kernel<P, OPT>), k3_lds_bytes<P>());
+  return f;
 }
 
-hipError_t stage_k3_f64(const StageParams<double> &prm, unsigned grid, int options,
-                        hipStream_t st) {
+const void *stage_k3_f64(int options) {
   // bit 1 (keep the FP64 input) is implied in FP64
-  if (options & kOptStream) return launch_k3<double, kOptStream>(prm, grid, st);
-  return launch_k3<double, 0>(prm, grid, st);
+  if (options & kOptStream) return k3_fn<double, kOptStream>();
+  return k3_fn<double, 0>();
 }
-hipError_t stage_k3_f32(const StageParams<float> &prm, unsigned grid, int options,
-                        hipStream_t st) {
+const void *stage_k3_f32(int options) {
   switch (options & 3) {
-    case 0: return launch_k3<float, 0>(prm, grid, st);
-    case 1: return launch_k3<float, 1>(prm, grid, st);
-    case 2: return launch_k3<float, 2>(prm, grid, st);
-    default: return launch_k3<float, 3>(prm, grid, st);
+    case 0: return k3_fn<float, 0>();
+    case 1: return k3_fn<float, 1>();
+    case 2: return k3_fn<float, 2>();
+    default: return k3_fn<float, 3>();
   }
 }
 

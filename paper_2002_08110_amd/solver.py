@@ -158,6 +158,17 @@ class Solver:
             setattr(p, k, int(v))
         check(self.lib.hd_set_plan(self.h, ctypes.byref(p)))
 
+    def apply_tuned_plan(self, cache=None, arch=None) -> bool:
+        """Set the plan the autotuner measured fastest for this (d, k,
+        precision) on this GPU architecture, if the cache holds one."""
+        from . import autotune
+        plan = autotune.lookup(self.d, self.k, self.precision,
+                               path=cache or autotune.DEFAULT_CACHE, arch=arch)
+        if plan is None:
+            return False
+        self.set_plan(**plan)
+        return True
+
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
             self.lib.hd_destroy(self.h)
@@ -171,8 +182,9 @@ class Solver:
 
 
 class Batch:
-    """hd_batch over bound Solvers of one precision: one persistent launch per
-    RK stage for all active solves, one hipGraph replay per step."""
+    """hd_batch over bound Solvers (any d, degree, size, precision): per RK
+    stage one persistent launch per group of solves sharing a launch plan,
+    one hipGraph replay per step."""
 
     def __init__(self, solvers):
         self.lib = _hd.load()
@@ -198,18 +210,3 @@ class Batch:
             self.close()
         except Exception:
             pass
-
-
-def batch_plan(d, k, dim_v, precision):
-    """The launch plan the batched kernel uses for a (d, k, precision) solve;
-    a single Solver set to this plan computes bitwise the same stage."""
-    n = k + 1
-    psize = 4 if precision == "fp32" else 8
-    if d == 6 and k == 3:
-        return dict(kernel=1, options=3 if precision == "fp32" else 1, reg_dims=2, lds=1,
-                    cells_per_wg=1, wg_size=256, xcd_remap=0)
-    rd = 2 if (n <= 3 and dim_v >= 2) else 1
-    T = n ** (d - rd)
-    lds = T <= 256 and (256 // T) * n ** d * psize <= 40 * 1024
-    return dict(kernel=0, options=0, reg_dims=rd, lds=int(lds), cells_per_wg=256 // T if lds else 1,
-                wg_size=256, xcd_remap=0)

@@ -82,7 +82,8 @@ def all_plans(case: W.Case, precision="fp64"):
                                           wg_size=256, kernel=0))
     if k3_eligible(case):
         for xcd in (0, 1):
-            plans.append(dict(kernel=1, xcd_remap=xcd, reg_dims=2))
+            for opt in range(4):
+                plans.append(dict(kernel=1, xcd_remap=xcd, reg_dims=2, options=opt))
     return plans
 
 

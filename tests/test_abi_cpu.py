@@ -103,3 +103,33 @@ def test_plan_validation_without_gpu():
     q = hd_plan(lds=0, cells_per_wg=1, wg_size=128, xcd_remap=0, reg_dims=2)
     assert lib.hd_set_plan(h, ctypes.byref(q)) == 0
     lib.hd_destroy(h)
+
+
+@pytest.mark.parametrize("d,k,precision", [(d, k, p) for d in (2, 3, 4, 5, 6) for k in (1, 2, 3, 4, 5)
+                                           for p in ("fp64", "fp32")])
+def test_autotune_candidates_are_valid_plans(d, k, precision):
+    # Every plan the autotuner times passes the library's plan validation.
+    _lib()
+    from paper_2002_08110_amd import autotune
+    from paper_2002_08110_amd import workloads as W
+    from paper_2002_08110_amd.solver import Solver
+    dx, dv = W.SPLITS[d]
+    S = Solver(dx, dv, [2] * d, [0.0] * d, [1.0] * d, k, precision=precision, bind=False)
+    plans = autotune.candidate_plans(d, k, dv, precision)
+    assert plans
+    default = S.get_plan()
+    for plan in plans:
+        S.set_plan(**plan)
+    S.close()
+    assert any(all(default[key] == v for key, v in p.items()) for p in plans) or d == 6 and k == 5
+
+
+def test_autotune_cache_lookup(tmp_path):
+    import json
+    from paper_2002_08110_amd import autotune
+    path = tmp_path / "plans.json"
+    plan = dict(kernel=0, options=0, lds=1, cells_per_wg=4, reg_dims=1, xcd_remap=1, wg_size=256)
+    path.write_text(json.dumps({autotune.key("gfx950", 4, 3, "fp32"): {"plan": plan}}))
+    assert autotune.lookup(4, 3, "fp32", path=str(path), arch="gfx950") == plan
+    assert autotune.lookup(4, 3, "fp64", path=str(path), arch="gfx950") is None
+    assert autotune.lookup(4, 3, "fp32", path=str(tmp_path / "none.json"), arch="gfx950") is None

@@ -159,6 +159,37 @@ def test_constant_field_rk_matches_oracle(d, k, cells):
     assert rel_l2(S.get_state(), ref) <= TOL_FP64
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("d,k,cells", [(6, 3, [2, 1, 3, 2, 1, 2]), (4, 2, [3, 2, 2, 3]),
+                                       (5, 4, [1, 2, 1, 2, 2])])
+def test_rk_steps_match_oracle_for_every_plan(precision, d, k, cells):
+    # Every launch plan the autotuner may pick, in stage mode (the fused RK
+    # update, streaming options of the 6D degree-3 kernel included).
+    dx, dv = W.SPLITS[d]
+    if dx == dv:
+        case = W.phase_space_case("p", dx, dv, cells, k, 2)
+    else:
+        case = W.Case("c", dx, dv, cells, [0.0] * d, [1.0] * d, k, "constant",
+                      a=list(np.random.default_rng(d).uniform(-1, 1, d)), steps=2)
+    P = oracle_problem(case)
+    S = gpu_solver(case, precision)
+    dt = S.stable_dt(case.cfl)
+    u0 = W.random_state(P.ndofs, seed=13)
+    ref = P.rk_steps(u0, dt, case.steps)
+    tol = TOL_FP64 if precision == "fp64" else 1e-5
+    outs = {}
+    for plan in all_plans(case, precision):
+        S.set_plan(**plan)
+        S.set_state(u0)
+        S.rk_step(dt, case.steps)
+        got = S.get_state()
+        assert rel_l2(got, ref) <= tol, plan
+        outs.setdefault((plan.get("kernel", 0), plan["reg_dims"]), []).append(got)
+    for group in outs.values():
+        for o in group[1:]:
+            assert np.array_equal(o, group[0])
+
+
 def test_graph_replay_is_bitwise_equal_to_direct_stages():
     case = W.phase_space_case("p", 2, 2, [3, 2, 2, 3], 3, 3)
     u0 = W.random_state(case.ndofs, seed=9)
