@@ -74,7 +74,8 @@ typedef struct hd_batch hd_batch;    /* opaque */
 /* Launch plan of the fused stage kernel (chosen by the autotuner).
  *  lds:        1 = stage each cell's values in LDS for the sweeps along
  *              thread-distributed dimensions; 0 = read them from global memory.
- *  cells_per_wg: cells per workgroup (lds = 1) - ignored for lds = 0.
+ *  cells_per_wg: units per workgroup (lds = 1): cells, or slabs of cells if
+ *              split_dims > 0 - ignored for lds = 0.
  *  wg_size:    threads per workgroup for lds = 0 (multiple of 64, <= 1024).
  *  xcd_remap:  1 = map consecutive cell tiles to the same XCD.
  *  reg_dims:   number of slowest dimensions whose lines a thread keeps in
@@ -86,7 +87,13 @@ typedef struct hd_batch hd_batch;    /* opaque */
  *              increment du and stores of the output solution, so they do
  *              not displace cached neighbour data; bit 1 (kernel 1, FP32
  *              only): keep the FP64 input solution in registers instead of
- *              re-reading it for the update. */
+ *              re-reading it for the update.
+ *  split_dims: (kernel 0, lds = 1) number of velocity dimensions, just below
+ *              the register dimensions, along which a cell is cut into slabs
+ *              of one node layer each; a workgroup stages one slab in LDS and
+ *              reads the other slabs of the line from global memory. 0, 1 or
+ *              2; compiled for degree >= 4 at d >= 5, for cells too large to
+ *              stage whole. */
 typedef struct {
   int lds;
   int cells_per_wg;
@@ -95,6 +102,7 @@ typedef struct {
   int reg_dims;
   int kernel;
   int options;
+  int split_dims;
 } hd_plan;
 
 /* Create a solver for `mesh` and polynomial degree `degree` (k+1 nodes per

@@ -40,20 +40,34 @@ def candidate_plans(d, k, dim_v, precision):
     if d == 6 and k == 3:
         for opt in ((0, 1, 2, 3) if precision == "fp32" else (0, 1)):
             for xcd in (0, 1):
-                plans.append(dict(kernel=1, options=opt, xcd_remap=xcd))
+                plans.append(dict(kernel=1, options=opt, xcd_remap=xcd, split_dims=0))
     for rd in (1, 2):
         if rd > dim_v:
             continue
+        for sd in (1, 2):
+            # slabs of cells too large to stage whole (degree >= 4, d >= 5)
+            if n < 5 or d < 5 or rd + sd > dim_v or n ** (d - rd - sd) > 1024:
+                continue
+            Ts = n ** (d - rd - sd)
+            ub = n ** (d - sd) * psize
+            if ub > 160 * 1024:
+                continue
+            cpws = [1] if Ts > 256 else sorted({1, max(1, 256 // Ts)})
+            for cpw in cpws:
+                if cpw * ub <= 160 * 1024:
+                    for xcd in (0, 1):
+                        plans.append(dict(kernel=0, options=0, lds=1, cells_per_wg=cpw, reg_dims=rd,
+                                          split_dims=sd, xcd_remap=xcd, wg_size=256))
         T = n ** (d - rd)
         for xcd in (0, 1):
             plans.append(dict(kernel=0, options=0, lds=0, wg_size=256, reg_dims=rd, xcd_remap=xcd,
-                              cells_per_wg=1))
+                              cells_per_wg=1, split_dims=0))
             if T <= 1024 and nd * psize <= 160 * 1024:
                 cpws = [1] if T > 256 else sorted({1, max(1, 256 // T)})
                 for cpw in cpws:
                     if cpw * nd * psize <= 160 * 1024 and (T > 256 or cpw * T <= 256):
                         plans.append(dict(kernel=0, options=0, lds=1, cells_per_wg=cpw,
-                                          reg_dims=rd, xcd_remap=xcd, wg_size=256))
+                                          reg_dims=rd, xcd_remap=xcd, wg_size=256, split_dims=0))
     return plans
 
 

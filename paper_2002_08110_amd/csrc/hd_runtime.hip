@@ -75,26 +75,32 @@ bool valid_plan(const hd_solver *s, const hd_plan &p, std::string *why) {
     }
     return true;
   }
-  const int rd = p.reg_dims;
+  const int rd = p.reg_dims, sd = p.split_dims;
   if (rd < 1 || rd > 2 || rd > s->dv) {
     *why = "reg_dims must be 1 or 2 and at most dim_v";
     return false;
   }
-  int64_t T = 1;
-  for (int j = 0; j < s->d - rd; ++j) T *= s->n;
+  if (sd < 0 || sd > 2 || (sd > 0 && (!p.lds || rd + sd > s->dv || s->n < 5 || s->d < 5))) {
+    *why = "split_dims must be 0, 1 or 2, with lds = 1, reg_dims + split_dims <= dim_v, "
+           "degree >= 4 and d >= 5";
+    return false;
+  }
+  int64_t T = 1, unit = 1;  // threads and nodes of one unit (cell or slab)
+  for (int j = 0; j < s->d - rd - sd; ++j) T *= s->n;
+  for (int j = 0; j < s->d - sd; ++j) unit *= s->n;
   if (p.lds) {
-    const int64_t cell_bytes = s->nd * (int64_t)s->psize();
+    const int64_t unit_bytes = unit * (int64_t)s->psize();
     if (T > 1024 || p.cells_per_wg < 1 || p.cells_per_wg * T > 1024 ||
-        p.cells_per_wg * cell_bytes > (int64_t)hd::kMaxLdsBytes) {
+        p.cells_per_wg * unit_bytes > (int64_t)hd::kMaxLdsBytes) {
       *why = "LDS plan does not fit (threads <= 1024, LDS <= 160 KiB per workgroup)";
       return false;
     }
     if (T > 256 && p.cells_per_wg != 1) {
-      *why = "cells with more than 256 pencils take one cell per workgroup";
+      *why = "units with more than 256 pencils take one unit per workgroup";
       return false;
     }
     if (T <= 256 && p.cells_per_wg * T > 256) {
-      *why = "workgroups of cells with <= 256 pencils hold at most 256 threads";
+      *why = "workgroups of units with <= 256 pencils hold at most 256 threads";
       return false;
     }
   } else {
@@ -113,16 +119,32 @@ hd_plan default_plan(const hd_solver *s) {
   // Measured on MI355X: FP64 prefers two register dimensions up to degree 3
   // (16 nodes per thread), FP32 one.
   p.reg_dims = (s->dv >= 2 && (s->n <= 3 || (s->n == 4 && s->prec == HD_FP64))) ? 2 : 1;
-  int64_t T = 1;
-  for (int j = 0; j < s->d - p.reg_dims; ++j) T *= s->n;
-  const int64_t cell_bytes = s->nd * (int64_t)s->psize();
-  if (T <= 1024 && cell_bytes <= (int64_t)hd::kMaxLdsBytes) {
+  // Cells too large for LDS at degree 5 (d = 5, 6), and 6D degree 4 in
+  // FP64: slabs along one or two velocity dimensions (measured on MI355X).
+  if (s->n == 6 && s->d == 6) {
+    p.reg_dims = 1;
+    p.split_dims = 2;
+  } else if (s->n == 6 && s->d == 5) {
+    p.reg_dims = 1;
+    p.split_dims = 1;
+  } else if (s->n == 5 && s->d == 6 && s->prec == HD_FP64) {
+    p.reg_dims = 2;
+    p.split_dims = 1;
+  } else if (s->n == 5 && s->d == 6) {
+    p.reg_dims = 2;
+  }
+  int64_t T = 1, unit = 1;
+  for (int j = 0; j < s->d - p.reg_dims - p.split_dims; ++j) T *= s->n;
+  for (int j = 0; j < s->d - p.split_dims; ++j) unit *= s->n;
+  const int64_t unit_bytes = unit * (int64_t)s->psize();
+  if (T <= 1024 && unit_bytes <= (int64_t)hd::kMaxLdsBytes) {
     p.lds = 1;
     int cpw = T <= 256 ? (int)(256 / T) : 1;
-    while (cpw > 1 && cpw * cell_bytes > (int64_t)hd::kMaxLdsBytes) --cpw;
+    while (cpw > 1 && cpw * unit_bytes > (int64_t)hd::kMaxLdsBytes) --cpw;
     p.cells_per_wg = std::max(1, cpw);
   } else {
     p.lds = 0;
+    p.split_dims = 0;
     p.cells_per_wg = 1;
   }
   p.kernel = k3_eligible(s) ? 1 : 0;
@@ -142,13 +164,16 @@ hd::LaunchShape hd::rt::shape_of(const hd_solver *s) {
     ls.shmem = s->prec == HD_FP32 ? hd::k3_lds_bytes<float>() : hd::k3_lds_bytes<double>();
     return ls;
   }
-  int64_t T = 1;
-  for (int j = 0; j < s->d - s->plan.reg_dims; ++j) T *= s->n;
+  const int sd = s->plan.split_dims;
+  int64_t T = 1, per_cell = 1;  // threads per unit, units per cell
+  for (int j = 0; j < s->d - s->plan.reg_dims - sd; ++j) T *= s->n;
+  for (int j = 0; j < sd; ++j) per_cell *= s->n;
   if (s->plan.lds) {
     const int64_t cpw = s->plan.cells_per_wg;
-    ls.grid = (unsigned)((s->ncells + cpw - 1) / cpw);
+    const int64_t units = s->ncells * per_cell;
+    ls.grid = (unsigned)((units + cpw - 1) / cpw);
     ls.block = (unsigned)(cpw * T);
-    ls.shmem = (size_t)(cpw * s->nd) * s->psize();
+    ls.shmem = (size_t)(cpw * (s->nd / per_cell)) * s->psize();
   } else {
     const int64_t total = s->ncells * T;
     ls.grid = (unsigned)((total + s->plan.wg_size - 1) / s->plan.wg_size);
@@ -165,13 +190,13 @@ const void *stage_entry(const hd_solver *s) {
   const bool f32 = s->prec == HD_FP32;
   if (s->plan.kernel == 1) return f32 ? hd::stage_k3_f32(s->plan.options)
                                       : hd::stage_k3_f64(s->plan.options);
-  const int rd = s->plan.reg_dims, lds = s->plan.lds, n = s->n;
+  const int rd = s->plan.reg_dims, lds = s->plan.lds, n = s->n, sd = s->plan.split_dims;
   switch (s->d) {
-    case 2: return f32 ? hd::stage_d2_f32(n, rd, lds) : hd::stage_d2_f64(n, rd, lds);
-    case 3: return f32 ? hd::stage_d3_f32(n, rd, lds) : hd::stage_d3_f64(n, rd, lds);
-    case 4: return f32 ? hd::stage_d4_f32(n, rd, lds) : hd::stage_d4_f64(n, rd, lds);
-    case 5: return f32 ? hd::stage_d5_f32(n, rd, lds) : hd::stage_d5_f64(n, rd, lds);
-    case 6: return f32 ? hd::stage_d6_f32(n, rd, lds) : hd::stage_d6_f64(n, rd, lds);
+    case 2: return f32 ? hd::stage_d2_f32(n, rd, lds, sd) : hd::stage_d2_f64(n, rd, lds, sd);
+    case 3: return f32 ? hd::stage_d3_f32(n, rd, lds, sd) : hd::stage_d3_f64(n, rd, lds, sd);
+    case 4: return f32 ? hd::stage_d4_f32(n, rd, lds, sd) : hd::stage_d4_f64(n, rd, lds, sd);
+    case 5: return f32 ? hd::stage_d5_f32(n, rd, lds, sd) : hd::stage_d5_f64(n, rd, lds, sd);
+    case 6: return f32 ? hd::stage_d6_f32(n, rd, lds, sd) : hd::stage_d6_f64(n, rd, lds, sd);
   }
   return nullptr;
 }
@@ -209,6 +234,9 @@ hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, in
     prm.dt = (P)dt;
   }
   if (ls.grid == 0) return HD_OK;
+  if ((uint64_t)ls.grid * ls.block >= (uint64_t(1) << 32))
+    return fail(HD_ERR_UNSUPPORTED, "stage launch exceeds 2^32 work-items; use a plan with more "
+                                    "nodes per thread");
   const void *fn = hd::rt::stage_entry(s);
   if (!fn) return fail(HD_ERR_HIP, "no compiled stage kernel for this plan");
   void *args[] = {&prm};

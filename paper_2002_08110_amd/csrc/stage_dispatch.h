@@ -32,17 +32,36 @@ constexpr bool lds_variant_ok() {
   return ipow(N, D - RD) <= 1024 && (size_t)ipow(N, D) * sizeof(P) <= kMaxLdsBytes;
 }
 
-template <int D, int N, int DX, int RD, typename P, bool LDS>
+// True if the slab variant (SD split dims) of (D, N, RD, P) is compiled: it
+// serves the cells that do not fit LDS whole (degree >= 4, d >= 5), and a
+// slab must fit one workgroup and its LDS.
+template <int D, int N, int DX, int RD, int SD, typename P>
+constexpr bool split_variant_ok() {
+  return SD >= 1 && N >= 5 && D >= 5 && RD + SD <= D - DX && D - RD - SD >= DX &&
+         ipow(N, D - RD - SD) <= 1024 &&
+         (size_t)ipow(N, D - SD) * sizeof(P) <= kMaxLdsBytes;
+}
+
+template <int D, int N, int DX, int RD, typename P, bool LDS, int SD = 0>
 const void *variant_fn() {
   static const void *const f = [] {
-    const void *k = reinterpret_cast<const void *>(&stage_kernel<D, N, DX, RD, P, LDS>);
+    const void *k = reinterpret_cast<const void *>(&stage_kernel<D, N, DX, RD, P, LDS, SD>);
     return LDS ? allow_max_lds(k, kMaxLdsBytes) : k;
   }();
   return f;
 }
 
 template <int D, int N, int DX, int RD, typename P>
-const void *resolve_lds(int lds) {
+const void *resolve_lds(int lds, int sd) {
+  if (sd == 1) {
+    if constexpr (split_variant_ok<D, N, DX, RD, 1, P>()) return lds ? variant_fn<D, N, DX, RD, P, true, 1>() : nullptr;
+    return nullptr;
+  }
+  if (sd == 2) {
+    if constexpr (split_variant_ok<D, N, DX, RD, 2, P>()) return lds ? variant_fn<D, N, DX, RD, P, true, 2>() : nullptr;
+    return nullptr;
+  }
+  if (sd != 0) return nullptr;
   if (lds) {
     if constexpr (lds_variant_ok<D, N, RD, P>()) return variant_fn<D, N, DX, RD, P, true>();
     else return nullptr;
@@ -51,39 +70,41 @@ const void *resolve_lds(int lds) {
 }
 
 template <int D, int N, int DX, typename P>
-const void *resolve_rd(int rd, int lds) {
+const void *resolve_rd(int rd, int lds, int sd) {
   constexpr int DV = D - DX;
-  if (rd == 1) return resolve_lds<D, N, DX, 1, P>(lds);
+  if (rd == 1) return resolve_lds<D, N, DX, 1, P>(lds, sd);
   if constexpr (DV >= 2) {
-    if (rd == 2) return resolve_lds<D, N, DX, 2, P>(lds);
+    if (rd == 2) return resolve_lds<D, N, DX, 2, P>(lds, sd);
   }
   return nullptr;
 }
 
 template <int D, int DX, typename P>
-const void *resolve_n(int n, int rd, int lds) {
+const void *resolve_n(int n, int rd, int lds, int sd) {
   switch (n) {
-    case 2: return resolve_rd<D, 2, DX, P>(rd, lds);
-    case 3: return resolve_rd<D, 3, DX, P>(rd, lds);
-    case 4: return resolve_rd<D, 4, DX, P>(rd, lds);
-    case 5: return resolve_rd<D, 5, DX, P>(rd, lds);
-    case 6: return resolve_rd<D, 6, DX, P>(rd, lds);
+    case 2: return resolve_rd<D, 2, DX, P>(rd, lds, sd);
+    case 3: return resolve_rd<D, 3, DX, P>(rd, lds, sd);
+    case 4: return resolve_rd<D, 4, DX, P>(rd, lds, sd);
+    case 5: return resolve_rd<D, 5, DX, P>(rd, lds, sd);
+    case 6: return resolve_rd<D, 6, DX, P>(rd, lds, sd);
     default: return nullptr;
   }
 }
 
 // Defined in stage_dN_fP.hip (one per dimension and precision): the entry of
-// the generic kernel for n = degree + 1 nodes per dimension, or nullptr.
-const void *stage_d2_f64(int n, int rd, int lds);
-const void *stage_d3_f64(int n, int rd, int lds);
-const void *stage_d4_f64(int n, int rd, int lds);
-const void *stage_d5_f64(int n, int rd, int lds);
-const void *stage_d6_f64(int n, int rd, int lds);
-const void *stage_d2_f32(int n, int rd, int lds);
-const void *stage_d3_f32(int n, int rd, int lds);
-const void *stage_d4_f32(int n, int rd, int lds);
-const void *stage_d5_f32(int n, int rd, int lds);
-const void *stage_d6_f32(int n, int rd, int lds);
+// the generic kernel for n = degree + 1 nodes per dimension, rd register
+// dims, LDS mode and sd split dims, or nullptr if that variant is not
+// compiled.
+const void *stage_d2_f64(int n, int rd, int lds, int sd);
+const void *stage_d3_f64(int n, int rd, int lds, int sd);
+const void *stage_d4_f64(int n, int rd, int lds, int sd);
+const void *stage_d5_f64(int n, int rd, int lds, int sd);
+const void *stage_d6_f64(int n, int rd, int lds, int sd);
+const void *stage_d2_f32(int n, int rd, int lds, int sd);
+const void *stage_d3_f32(int n, int rd, int lds, int sd);
+const void *stage_d4_f32(int n, int rd, int lds, int sd);
+const void *stage_d5_f32(int n, int rd, int lds, int sd);
+const void *stage_d6_f32(int n, int rd, int lds, int sd);
 
 // Specialised kernel for d = 6 (3 x + 3 v), degree 3: one cell per
 // 256-thread workgroup (stage_k3.hip); options as in hd_plan.

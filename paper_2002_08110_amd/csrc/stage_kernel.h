@@ -1,12 +1,18 @@
 // Fused element-centric DG advection stage kernel for gfx950.
 //
 // One thread owns a "pencil": the (k+1)^RD nodes of one cell that share the
-// thread's index in the NF = d - RD fastest node dimensions. Derivatives
-// along the RD slowest dimensions act on the thread's own registers;
-// derivatives along the NF fast dimensions read the other nodes of the line
-// from LDS (the cell is staged there once) or from global memory. Every
-// output value is written by exactly one thread and the input vector is
-// read-only, so the element-centric loop is race free (Sec. 2.6).
+// thread's index in the NF fastest node dimensions. Derivatives along the RD
+// slowest dimensions act on the thread's own registers; derivatives along
+// the NF fast dimensions read the other nodes of the line from LDS (the
+// cell is staged there once) or from global memory. Cells too large for LDS
+// can be cut into slabs along SD "split" dimensions (velocity dimensions
+// between the fast and the register ones): a workgroup then stages one slab,
+// the nodes with one fixed digit tuple in the split dimensions, and the
+// derivatives along a split dimension read the other slabs of the cell from
+// global memory (cache hits: the slabs of a cell run on neighbouring
+// workgroups). Every output value is written by exactly one thread and the
+// input vector is read-only, so the element-centric loop is race free
+// (Sec. 2.6).
 //
 // Per node i of cell c the kernel evaluates, for each dimension j,
 //   -a_j/h_j * sum_m D[i_j][m] u_{i_j->m}                    (volume)
@@ -20,6 +26,8 @@
 // inflow face. The inverse mass matrix is diagonal (collocation) and is
 // folded into the coefficients. a_j never depends on x_j for the supported
 // fields (constant; a_x = v, a_v = E(x)), so a_j factors out of the line sum.
+// The dimensions contribute in the order j = 1..d (volume, then face) in
+// every variant.
 //
 // The low-storage RK update (Sec. 5.4) is fused into the same pass:
 //   du <- A_s du + dt L(u),  u_out <- u_in + B_s du.
@@ -97,32 +105,40 @@ __device__ __forceinline__ P to_p(double v) {
 }
 
 // Largest workgroup a variant is launched with: 256 threads, except the LDS
-// variant of cells with more than 256 pencils (one cell per workgroup).
-template <int D, int N, int RD, bool USE_LDS>
+// variant of units (cells or slabs) with more than 256 pencils, which takes
+// one unit per workgroup (its pencil count, rounded up to whole waves).
+template <int D, int N, int RD, bool USE_LDS, int SD = 0>
 constexpr int stage_max_threads() {
-  return (USE_LDS && ipow(N, D - RD) > 256) ? 1024 : 256;
+  constexpr int T = ipow(N, D - RD - SD);
+  return (USE_LDS && T > 256) ? (T + 63) / 64 * 64 : 256;
 }
 
-// One workgroup's share of a stage: the cell tile `tile`. Called by the
-// stage kernel below and by the batched persistent kernel, which loops over
-// tiles of several solves (lds_reuse: the LDS of a previous tile may still be
-// read by other threads, so wait before overwriting it).
-template <int D, int N, int DX, int RD, typename P, bool USE_LDS>
+// One workgroup's share of a stage: the tile `tile` (cells_per_wg units -
+// cells, or slabs of cells if SD > 0 - for the LDS variant; blockDim.x
+// pencils otherwise). lds_reuse: the LDS of a previous tile may still be
+// read by other threads, so wait before overwriting it.
+template <int D, int N, int DX, int RD, typename P, bool USE_LDS, int SD = 0>
 __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned tile, P *lds,
                                            bool lds_reuse) {
   constexpr int DV = D - DX;
-  static_assert(RD >= 1 && RD <= DV, "register dims must be velocity dims");
-  constexpr int NF = D - RD;          // thread-distributed (fast) dims
+  static_assert(RD >= 1 && RD + SD <= DV, "register and split dims must be velocity dims");
+  static_assert(SD == 0 || USE_LDS, "split dims need the LDS variant");
+  constexpr int NF = D - RD - SD;     // thread-distributed (fast) dims
   constexpr int ND = ipow(N, D);      // nodes per cell
-  constexpr int T = ipow(N, NF);      // threads per cell
+  constexpr int T = ipow(N, NF);      // threads per unit
   constexpr int NS = ipow(N, RD);     // nodes per thread
+  constexpr int NU = ipow(N, SD);     // units (slabs) per cell
+  constexpr int SST = ipow(N, NF + SD);  // node stride of the first register dim
+  constexpr int UN = T * NS;          // nodes per unit
   static_assert(DX <= NF, "all x dims are thread-distributed");
 
-  unsigned cell, f, lc = 0;
+  unsigned cell, f, lc = 0, unit = 0;
   if constexpr (USE_LDS) {
     lc = threadIdx.x / T;
     f = threadIdx.x - lc * T;
-    cell = tile * prm.cells_per_wg + lc;
+    const unsigned U = tile * prm.cells_per_wg + lc;
+    cell = U / NU;
+    unit = U - cell * NU;
   } else {
     const uint64_t p = (uint64_t)tile * blockDim.x + threadIdx.x;
     cell = (unsigned)(p / T);
@@ -151,16 +167,29 @@ __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned t
     }
   }
 
-  const uint64_t base = (uint64_t)cl * ND + f;
+  // Split digits of this unit and the unit's node offset in the cell.
+  int sd[SD > 0 ? SD : 1];
+  unsigned soff = 0;
+  {
+    unsigned r = unit;
+#pragma unroll
+    for (int k = 0; k < SD; ++k) {
+      sd[k] = (int)(r % N);
+      r /= N;
+      soff += (unsigned)sd[k] * (unsigned)ipow(N, NF + k);
+    }
+  }
+
+  const uint64_t base = (uint64_t)cl * ND + f + soff;
   P u[NS];
 #pragma unroll
-  for (int s = 0; s < NS; ++s) u[s] = to_p<P>(prm.u_in[base + (uint64_t)s * T]);
+  for (int s = 0; s < NS; ++s) u[s] = to_p<P>(prm.u_in[base + (uint64_t)s * SST]);
   const bool stage = prm.mode == 1;
   if constexpr (USE_LDS) {
     if (lds_reuse) __syncthreads();
     if (active) {
 #pragma unroll
-      for (int s = 0; s < NS; ++s) lds[lc * ND + f + s * T] = u[s];
+      for (int s = 0; s < NS; ++s) lds[lc * UN + f + s * T] = u[s];
     }
     __syncthreads();
     if (!active) return;
@@ -168,8 +197,8 @@ __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned t
 
   // Field at this thread's nodes. x dims are all fast, so E is per thread.
   P ev[DV];
-  P vth[DX];   // velocity for x-dim j if its velocity dim is fast
-  P vbase[DX]; // lo + c h for x-dim j if its velocity dim is slow
+  P vth[DX];   // velocity for x-dim j if its velocity dim is fast or split
+  P vbase[DX]; // lo + c h for x-dim j if its velocity dim is a register dim
   const bool phase = prm.field_kind == 1;
   if (phase) {
     unsigned xcell = 0, xs = 1, xnode = 0, ns = 1;
@@ -188,6 +217,7 @@ __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned t
       const int m = DX + j;
       vbase[j] = prm.vlo[m] + P(c[m]) * prm.vh[m];
       if (m < NF) vth[j] = vbase[j] + prm.xi[fd[m]] * prm.vh[m];
+      else if (m < NF + SD) vth[j] = vbase[j] + prm.xi[sd[m - NF]] * prm.vh[m];
       else vth[j] = P(0);
     }
   } else {
@@ -203,8 +233,8 @@ __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned t
   auto a_at = [&](int j, int s) -> P {
     if (j >= DX) return ev[j - DX];
     const int m = DX + j;
-    if (!phase || m < NF) return vth[j];
-    const int r = m - NF;
+    if (!phase || m < NF + SD) return vth[j];
+    const int r = m - NF - SD;
     const int dig = (s / ipow(N, r)) % N;
     return vbase[j] + prm.xi[dig] * prm.vh[m];
   };
@@ -222,7 +252,7 @@ __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned t
   P nbs[RD][NL];
 #pragma unroll
   for (int r = 0; r < RD; ++r) {
-    const int j = NF + r;
+    const int j = NF + SD + r;
     const int sstride = ipow(N, r);
     const unsigned cj = c[j], nj = prm.cells[j], st = prm.cstride[j];
     const unsigned left = cj == 0 ? cl + (nj - 1) * st : cl - st;
@@ -235,14 +265,14 @@ __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned t
       const bool useL = a > P(0), useR = a < P(0);
       const unsigned cc = useL ? left : (useR ? right : cl);
       const int sn = useL ? sk : s;
-      nbs[r][l] = to_p<P>(prm.u_in[(uint64_t)cc * ND + f + (uint64_t)sn * T]);
+      nbs[r][l] = to_p<P>(prm.u_in[(uint64_t)cc * ND + f + soff + (uint64_t)sn * SST]);
     }
   }
   constexpr bool kPrefetchDu = sizeof(P) == 4 || NS <= 4;
   P dv[NS];
   if (kPrefetchDu && stage && prm.read_du) {
 #pragma unroll
-    for (int s = 0; s < NS; ++s) dv[s] = prm.du[base + (uint64_t)s * T];
+    for (int s = 0; s < NS; ++s) dv[s] = prm.du[base + (uint64_t)s * SST];
   }
   sched_fence();
 
@@ -265,7 +295,7 @@ __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned t
 #pragma unroll
       for (int m = 0; m < N; ++m) {
         P v;
-        if constexpr (USE_LDS) v = lds[lc * ND + off0 + m * stride + s * T];
+        if constexpr (USE_LDS) v = lds[lc * UN + off0 + m * stride + s * T];
         else v = to_p<P>(prm.u_in[(uint64_t)cl * ND + off0 + m * stride + (uint64_t)s * T]);
         sum += row[m] * v;
       }
@@ -283,7 +313,54 @@ __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned t
         const bool useL = onL && a > P(0), useR = onR && a < P(0);
         const unsigned cc = useL ? left : (useR ? right : cl);
         const int node = (int)f + (useL ? (N - 1) * stride : (useR ? -(N - 1) * stride : 0));
-        nb[s] = to_p<P>(prm.u_in[(uint64_t)cc * ND + node + (uint64_t)s * T]);
+        nb[s] = to_p<P>(prm.u_in[(uint64_t)cc * ND + soff + node + (uint64_t)s * SST]);
+      }
+      const P lf = prm.lift_inv_h[j];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const P a = a_at(j, s);
+        const bool useL = onL && a > P(0), useR = onR && a < P(0);
+        const P w = useL ? lf * a : (useR ? -lf * a : P(0));
+        acc[s] += w * (nb[s] - u[s]);
+      }
+    }
+    sched_fence();
+  }
+
+  // ---- split dimensions: the other slabs of the line from global memory ----
+#pragma unroll
+  for (int k = 0; k < SD; ++k) {
+    const int j = NF + k;
+    const int stride = ipow(N, j);
+    const int ij = sd[k];
+    const unsigned cj = c[j], nj = prm.cells[j], st = prm.cstride[j];
+    const unsigned left = cj == 0 ? cl + (nj - 1) * st : cl - st;
+    const unsigned right = cj == nj - 1 ? cl - (nj - 1) * st : cl + st;
+    P row[N];
+#pragma unroll
+    for (int m = 0; m < N; ++m) row[m] = prm.Dm[ij * N + m];
+    const uint64_t line0 = (uint64_t)cl * ND + f + soff - (unsigned)(ij * stride);
+    const P ih = prm.inv_h[j];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      P v[N];
+#pragma unroll
+      for (int m = 0; m < N; ++m) v[m] = to_p<P>(prm.u_in[line0 + m * stride + (uint64_t)s * SST]);
+      P sum = P(0);
+#pragma unroll
+      for (int m = 0; m < N; ++m) sum += row[m] * v[m];
+      acc[s] -= a_at(j, s) * ih * sum;
+    }
+    if (ij == 0 || ij == N - 1) {
+      const bool onL = ij == 0, onR = ij == N - 1;
+      P nb[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const P a = a_at(j, s);
+        const bool useL = onL && a > P(0), useR = onR && a < P(0);
+        const unsigned cc = useL ? left : (useR ? right : cl);
+        const int node = (int)(f + soff) + (useL ? (N - 1) * stride : (useR ? -(N - 1) * stride : 0));
+        nb[s] = to_p<P>(prm.u_in[(uint64_t)cc * ND + node + (uint64_t)s * SST]);
       }
       const P lf = prm.lift_inv_h[j];
 #pragma unroll
@@ -300,7 +377,7 @@ __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned t
   // ---- slow (register) dimensions ----
 #pragma unroll
   for (int r = 0; r < RD; ++r) {
-    const int j = NF + r;
+    const int j = NF + SD + r;
     const int sstride = ipow(N, r);
     const P ih = prm.inv_h[j];
     const P lf = prm.lift_inv_h[j];
@@ -328,7 +405,7 @@ __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned t
   // ---- output ----
   if (!stage) {
 #pragma unroll
-    for (int s = 0; s < NS; ++s) prm.out[base + (uint64_t)s * T] = acc[s];
+    for (int s = 0; s < NS; ++s) prm.out[base + (uint64_t)s * SST] = acc[s];
     return;
   }
   // FP64 with many nodes per thread reads the increment only now, keeping
@@ -336,7 +413,7 @@ __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned t
   if (prm.read_du) {
     if (!kPrefetchDu) {
 #pragma unroll
-      for (int s = 0; s < NS; ++s) dv[s] = prm.du[base + (uint64_t)s * T];
+      for (int s = 0; s < NS; ++s) dv[s] = prm.du[base + (uint64_t)s * SST];
     }
 #pragma unroll
     for (int s = 0; s < NS; ++s) dv[s] = prm.rk_a * dv[s] + prm.dt * acc[s];
@@ -346,23 +423,23 @@ __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned t
   }
   if (prm.write_du) {
 #pragma unroll
-    for (int s = 0; s < NS; ++s) prm.du[base + (uint64_t)s * T] = dv[s];
+    for (int s = 0; s < NS; ++s) prm.du[base + (uint64_t)s * SST] = dv[s];
   }
   // FP64 solution update; in FP32 mode the FP64 input is re-read (cache hit).
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    const double uo = sizeof(P) == sizeof(double) ? (double)u[s] : prm.u_in[base + (uint64_t)s * T];
-    prm.u_out[base + (uint64_t)s * T] = uo + prm.rk_b * (double)dv[s];
+    const double uo = sizeof(P) == sizeof(double) ? (double)u[s] : prm.u_in[base + (uint64_t)s * SST];
+    prm.u_out[base + (uint64_t)s * SST] = uo + prm.rk_b * (double)dv[s];
   }
 }
 
-template <int D, int N, int DX, int RD, typename P, bool USE_LDS>
-__global__ void __launch_bounds__((stage_max_threads<D, N, RD, USE_LDS>()))
+template <int D, int N, int DX, int RD, typename P, bool USE_LDS, int SD = 0>
+__global__ void __launch_bounds__((stage_max_threads<D, N, RD, USE_LDS, SD>()))
     stage_kernel(const StageParams<P> prm) {
   extern __shared__ unsigned char smem_raw[];
   unsigned tile = blockIdx.x;
   if (prm.xcd_remap) tile = xcd_tile(tile, prm.nblocks);
-  stage_body<D, N, DX, RD, P, USE_LDS>(prm, tile, reinterpret_cast<P *>(smem_raw), false);
+  stage_body<D, N, DX, RD, P, USE_LDS, SD>(prm, tile, reinterpret_cast<P *>(smem_raw), false);
 }
 
 }  // namespace hd

@@ -69,21 +69,30 @@ def all_plans(case: W.Case, precision="fp64"):
     for rd in (1, 2):
         if rd > case.dim_v:
             continue
+        for sd in (1, 2):  # slab variants (degree >= 4, d >= 5)
+            Ts = n ** (d - rd - sd)
+            if n < 5 or d < 5 or rd + sd > case.dim_v or Ts > 1024:
+                continue
+            ub = n ** (d - sd) * psize
+            for cpw in ([1] if Ts > 256 else sorted({1, max(1, 256 // Ts)})):
+                if cpw * ub <= 160 * 1024:
+                    plans.append(dict(lds=1, cells_per_wg=cpw, reg_dims=rd, split_dims=sd,
+                                      xcd_remap=cpw % 2, wg_size=256, kernel=0))
         T = n ** (d - rd)
         for xcd in (0, 1):
             for wg in (64, 256):
                 plans.append(dict(lds=0, wg_size=wg, reg_dims=rd, xcd_remap=xcd, cells_per_wg=1,
-                                  kernel=0))
+                                  kernel=0, split_dims=0))
             if T <= 1024 and nd * psize <= 160 * 1024:
                 cpws = [1] if T > 256 else sorted({1, max(1, 256 // T)})
                 for cpw in cpws:
                     if cpw * nd * psize <= 160 * 1024:
                         plans.append(dict(lds=1, cells_per_wg=cpw, reg_dims=rd, xcd_remap=xcd,
-                                          wg_size=256, kernel=0))
+                                          wg_size=256, kernel=0, split_dims=0))
     if k3_eligible(case):
         for xcd in (0, 1):
             for opt in range(4):
-                plans.append(dict(kernel=1, xcd_remap=xcd, reg_dims=2, options=opt))
+                plans.append(dict(kernel=1, xcd_remap=xcd, reg_dims=2, options=opt, split_dims=0))
     return plans
 
 
