@@ -40,11 +40,18 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--precisions", default="fp64,fp32")
     ap.add_argument("--plan", default="", help="override plan, e.g. lds=1,reg_dims=1")
-    ap.add_argument("--mode", default="bench", choices=["bench", "stages", "copy", "batch"],
+    ap.add_argument("--mode", default="bench",
+                    choices=["bench", "stages", "copy", "batch", "serve"],
                     help="stages: only run --steps x 5 stage launches per precision (for "
                          "profilers); copy: a plain device copy of --copy-mib MiB (the "
-                         "calibration kernel for the byte counters)")
+                         "calibration kernel for the byte counters); batch: the 96-solve "
+                         "mix; serve: a prefix of the seeded request trace")
     ap.add_argument("--copy-mib", type=int, default=4096)
+    ap.add_argument("--requests", type=int, default=24, help="serve: trace prefix length")
+    ap.add_argument("--steps-scale", type=float, default=1.0,
+                    help="serve: factor on each request's step count")
+    ap.add_argument("--load", type=float, default=0.7,
+                    help="serve: offered load of the second, stretched-arrival run (0: skip)")
     return ap.parse_args()
 
 
@@ -222,6 +229,42 @@ def run_batch(steps, seq_steps):
     print(json.dumps(res), flush=True)
 
 
+def run_serve(n_requests, steps_scale, load):
+    """The first n_requests requests of the seeded serving trace (Poisson
+    arrivals at 20 req/s; d in {4,5,6}, k in {2..5}, 1e6-2e9 DoFs), each
+    request's step count scaled by steps_scale, served with continuous
+    batching in FP32 operator mode, and one at a time in FP64 on the same
+    arrivals. A second batched run stretches the arrivals to the offered
+    load `load` (relative to the measured batched throughput). Prints one
+    JSON line."""
+    from paper_2002_08110_amd import serve
+    from paper_2002_08110_amd import workloads as W
+    trace = W.serve_trace()[:n_requests]
+    for q in trace:
+        q.case.steps = max(1, int(round(q.case.steps * steps_scale)))
+    work = float(sum(q.case.ndofs * q.case.steps * 5 for q in trace))
+    span = max(q.arrival for q in trace)
+
+    def log(msg):
+        print("# " + msg, file=sys.stderr, flush=True)
+
+    out = {"metric": "served DoF-updates/s and completion latency (request trace)",
+           "requests": len(trace), "steps_scale": steps_scale, "work_dof_updates": work,
+           "dofs_max": max(q.case.ndofs for q in trace),
+           "dofs_mean": float(np.mean([q.case.ndofs for q in trace]))}
+    _, b = serve.serve(trace, precision="fp32", batched=True, log=log)
+    log("batched fp32: %s" % json.dumps(b))
+    _, f = serve.serve(trace, precision="fp64", batched=False, log=log)
+    log("one-at-a-time fp64: %s" % json.dumps(f))
+    rho = work / b["dof_updates_per_s"] / span
+    out.update({"batched_fp32": b, "one_at_a_time_fp64": f, "offered_load": rho})
+    if load > 0:
+        scale = rho / load
+        _, c = serve.serve(trace, precision="fp32", batched=True, time_scale=scale, log=log)
+        out["stretched"] = {"offered_load": load, "time_scale": scale, "batched_fp32": c}
+    print(json.dumps(out), flush=True)
+
+
 def profiled_traffic(precision, plan_override):
     """Bytes per stage launch from the committed byte-counter profile of the
     default plan, or None if the kernel source changed since it was taken."""
@@ -272,7 +315,7 @@ def cpu_baseline(case, seconds):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     import torch
@@ -293,6 +336,9 @@ def main():
         return
     if args.mode == "batch":
         run_batch(args.steps, max(1, args.steps // 5))
+        return
+    if args.mode == "serve":
+        run_serve(args.requests, args.steps_scale, args.load)
         return
     if args.mode == "stages":
         for prec in args.precisions.split(","):

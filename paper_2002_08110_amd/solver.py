@@ -170,9 +170,13 @@ class Solver:
         return True
 
     def close(self):
+        """Destroy the handle and drop the workspace (device memory returns
+        to torch's allocator)."""
         if getattr(self, "h", None) is not None and self.h.value:
             self.lib.hd_destroy(self.h)
             self.h = ctypes.c_void_p()
+        self.workspace = None
+        self._ws_raw = None
 
     def __del__(self):
         try:
