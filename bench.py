@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=24, help="serve: trace prefix length")
     ap.add_argument("--steps-scale", type=float, default=1.0,
                     help="serve: factor on each request's step count")
+    ap.add_argument("--fill-dofs", type=float, default=1e8,
+                    help="serve: DoFs a batched step aims to cover")
     ap.add_argument("--load", type=float, default=0.7,
                     help="serve: offered load of the second, stretched-arrival run (0: skip)")
     return ap.parse_args()
@@ -229,7 +231,7 @@ def run_batch(steps, seq_steps):
     print(json.dumps(res), flush=True)
 
 
-def run_serve(n_requests, steps_scale, load):
+def run_serve(n_requests, steps_scale, load, fill):
     """The first n_requests requests of the seeded serving trace (Poisson
     arrivals at 20 req/s; d in {4,5,6}, k in {2..5}, 1e6-2e9 DoFs), each
     request's step count scaled by steps_scale, served with continuous
@@ -252,7 +254,7 @@ def run_serve(n_requests, steps_scale, load):
            "requests": len(trace), "steps_scale": steps_scale, "work_dof_updates": work,
            "dofs_max": max(q.case.ndofs for q in trace),
            "dofs_mean": float(np.mean([q.case.ndofs for q in trace]))}
-    _, b = serve.serve(trace, precision="fp32", batched=True, log=log)
+    _, b = serve.serve(trace, precision="fp32", batched=True, log=log, fill_dofs=fill)
     log("batched fp32: %s" % json.dumps(b))
     _, f = serve.serve(trace, precision="fp64", batched=False, log=log)
     log("one-at-a-time fp64: %s" % json.dumps(f))
@@ -260,7 +262,8 @@ def run_serve(n_requests, steps_scale, load):
     out.update({"batched_fp32": b, "one_at_a_time_fp64": f, "offered_load": rho})
     if load > 0:
         scale = rho / load
-        _, c = serve.serve(trace, precision="fp32", batched=True, time_scale=scale, log=log)
+        _, c = serve.serve(trace, precision="fp32", batched=True, time_scale=scale, log=log,
+                           fill_dofs=fill)
         out["stretched"] = {"offered_load": load, "time_scale": scale, "batched_fp32": c}
     print(json.dumps(out), flush=True)
 
@@ -338,7 +341,7 @@ def main():
         run_batch(args.steps, max(1, args.steps // 5))
         return
     if args.mode == "serve":
-        run_serve(args.requests, args.steps_scale, args.load)
+        run_serve(args.requests, args.steps_scale, args.load, args.fill_dofs)
         return
     if args.mode == "stages":
         for prec in args.precisions.split(","):

@@ -4,11 +4,17 @@ Requests (advection solves: mesh, degree, field, initial state, number of
 LSRK steps) arrive over time. The server admits them in arrival order as
 soon as their device footprint (hd_required_bytes: two FP64 solution
 buffers, the stage increment and the field table) fits the memory budget,
-keeps their state resident on the GPU, and advances every admitted request
-by one LSRK step per iteration with one batched hipGraph replay
-(hd_batch_step). A request that arrives while others run joins at the next
-step boundary; a finished request frees its memory at once. The loop is
-host bookkeeping only: every stage runs in the library's kernels.
+keeps their state resident on the GPU, and advances admitted requests one
+LSRK step per iteration with one batched hipGraph replay (hd_batch_step).
+Each step takes resident requests until their DoFs fill the GPU (fill_dofs,
+at least one request), shortest remaining work first (order="shortest") or
+in arrival order (order="arrival"): small requests share steps and overlap
+on the device instead of queueing behind a large one, whose steps cost the
+same whether or not it shares them. A request that arrives while others run
+joins at the next step boundary; a finished request frees its memory at
+once.
+The loop is host bookkeeping only: every stage runs in the library's
+kernels.
 
 Times are wall-clock seconds from the start of the run; latency is
 completion minus arrival, service time completion minus admission.
@@ -86,10 +92,15 @@ class _Running:
 
 
 def serve(requests, precision="fp32", budget=None, batched=True, keep_states=False,
-          time_scale=1.0, tuned=True, log=None):
+          time_scale=1.0, tuned=True, log=None, fill_dofs=1e8, order="shortest"):
     """Run `requests` (workloads.Request, arrival-ordered) through the
     server. batched=False serves one request at a time (the baseline).
-    time_scale multiplies the arrival times. Returns (results, stats)."""
+    time_scale multiplies the arrival times; fill_dofs is the DoF count a
+    batched step aims to cover (None: every resident request steps each
+    iteration); order picks which resident requests fill a step. Returns
+    (results, stats)."""
+    if order not in ("shortest", "arrival"):
+        raise ValueError("order must be 'shortest' or 'arrival'")
     budget = default_budget() if budget is None else int(budget)
     reqs = sorted(requests, key=lambda r: r.arrival)
     results = {r.rid: Result(r.rid, r.arrival * time_scale, ndofs=r.case.ndofs,
@@ -142,9 +153,20 @@ def serve(requests, precision="fp32", budget=None, batched=True, keep_states=Fal
                     batch.close()
                 batch = Batch([x.solver for x in running])
                 members = ids
+            # The stepping set: by the policy's order until the GPU is filled.
+            pick = list(range(len(running)))
+            if order == "shortest":
+                pick.sort(key=lambda i: (running[i].res.ndofs * running[i].left, i))
+            act, tot = [0] * len(running), 0
+            for i in pick:
+                if tot > 0 and fill_dofs is not None and tot >= fill_dofs:
+                    break
+                act[i] = 1
+                tot += running[i].res.ndofs
+            stepping = [x for x, a in zip(running, act) if a]
             # Several steps per check when no request finishes and none can
             # arrive before they are done: fewer host round trips.
-            k = min(x.left for x in running)
+            k = min(x.left for x in stepping)
             if waiting:
                 k = 1
             elif nxt < len(reqs):
@@ -154,8 +176,8 @@ def serve(requests, precision="fp32", budget=None, batched=True, keep_states=Fal
             ts = time.perf_counter()
             dts = [x.dt for x in running]
             for _ in range(k):
-                batch.step(dts)
-            for x in running:
+                batch.step(dts, active=act)
+            for x in stepping:
                 x.left -= k
             steps_run += k
         else:
@@ -196,5 +218,6 @@ def serve(requests, precision="fp32", budget=None, batched=True, keep_states=Fal
         "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
         "service_p50_s": float(np.percentile(svc, 50)), "service_p99_s": float(np.percentile(svc, 99)),
         "peak_bytes": peak, "budget_bytes": budget, "batched": batched, "precision": precision,
+        "fill_dofs": fill_dofs if batched else None, "order": order if batched else "arrival",
     }
     return res, stats

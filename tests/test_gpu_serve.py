@@ -29,11 +29,16 @@ def alone(case, precision):
     return out, dt
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_served_results_equal_alone(precision):
+@pytest.mark.parametrize("precision,fill,order", [
+    ("fp32", 1e8, "shortest"), ("fp64", 1e8, "shortest"), ("fp32", 3e4, "shortest"),
+    ("fp32", 3e4, "arrival"), ("fp64", None, "arrival")])
+def test_served_results_equal_alone(precision, fill, order):
+    # fill: DoFs a step aims to cover (3e4: a few requests per step, the
+    # rest resident and inactive; None: every resident request each step)
     from paper_2002_08110_amd import serve
     reqs = small_trace()
-    res, stats = serve.serve(reqs, precision=precision, keep_states=True)
+    res, stats = serve.serve(reqs, precision=precision, keep_states=True, fill_dofs=fill,
+                             order=order)
     assert stats["requests"] == len(reqs)
     by_id = {r.rid: r for r in res}
     for q in reqs:
