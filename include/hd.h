@@ -83,11 +83,13 @@ typedef struct hd_batch hd_batch;    /* opaque */
  *  kernel:     0 = the generic kernel (the fields above apply); 1 = the
  *              kernel specialised for d = 6 (3 x + 3 v) at degree 3, one cell
  *              per 256-thread workgroup (only xcd_remap and options apply).
- *  options:    bit 0: non-temporal (streaming) loads and stores of the stage
- *              increment du and stores of the output solution, so they do
- *              not displace cached neighbour data; bit 1 (kernel 1, FP32
- *              only): keep the FP64 input solution in registers instead of
- *              re-reading it for the update.
+ *  options:    bit 0 (both kernels): non-temporal (streaming) loads and
+ *              stores of the stage increment du and stores of the output
+ *              solution, so they do not displace cached neighbour data;
+ *              bit 1 (kernel 1, FP32 only): keep the FP64 input solution in
+ *              registers instead of re-reading it for the update (the
+ *              generic kernel does so by itself when a thread owns at most
+ *              8 nodes).
  *  split_dims: (kernel 0, lds = 1) number of velocity dimensions, just below
  *              the register dimensions, along which a cell is cut into slabs
  *              of one node layer each; a workgroup stages one slab in LDS and

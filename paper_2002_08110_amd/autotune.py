@@ -68,6 +68,9 @@ def candidate_plans(d, k, dim_v, precision):
                     if cpw * nd * psize <= 160 * 1024 and (T > 256 or cpw * T <= 256):
                         plans.append(dict(kernel=0, options=0, lds=1, cells_per_wg=cpw,
                                           reg_dims=rd, xcd_remap=xcd, wg_size=256, split_dims=0))
+    generic = [p for p in plans if p["kernel"] == 0]
+    for p in generic:  # the streaming option of the generic kernel
+        plans.append(dict(p, options=1))
     return plans
 
 

@@ -150,7 +150,10 @@ hd_plan default_plan(const hd_solver *s) {
   p.kernel = k3_eligible(s) ? 1 : 0;
   // Measured on MI355X (6D 8^6, k = 3): streaming du and the output solution
   // helps both precisions, keeping the FP64 input in registers helps FP32.
-  p.options = p.kernel == 1 ? (s->prec == HD_FP32 ? 3 : 1) : 0;
+  // The generic kernel streams them once the vectors outgrow the caches
+  // (the autotuner picked streaming for most (d, k) at 1.5e8 DoFs).
+  if (p.kernel == 1) p.options = s->prec == HD_FP32 ? 3 : 1;
+  else p.options = s->ndofs >= (int64_t(1) << 25) ? 1 : 0;
   return p;
 }
 
@@ -190,13 +193,14 @@ const void *stage_entry(const hd_solver *s) {
   const bool f32 = s->prec == HD_FP32;
   if (s->plan.kernel == 1) return f32 ? hd::stage_k3_f32(s->plan.options)
                                       : hd::stage_k3_f64(s->plan.options);
-  const int rd = s->plan.reg_dims, lds = s->plan.lds, n = s->n, sd = s->plan.split_dims;
+  const int rd = s->plan.reg_dims, lds = s->plan.lds, n = s->n, sd = s->plan.split_dims,
+            opt = s->plan.options;
   switch (s->d) {
-    case 2: return f32 ? hd::stage_d2_f32(n, rd, lds, sd) : hd::stage_d2_f64(n, rd, lds, sd);
-    case 3: return f32 ? hd::stage_d3_f32(n, rd, lds, sd) : hd::stage_d3_f64(n, rd, lds, sd);
-    case 4: return f32 ? hd::stage_d4_f32(n, rd, lds, sd) : hd::stage_d4_f64(n, rd, lds, sd);
-    case 5: return f32 ? hd::stage_d5_f32(n, rd, lds, sd) : hd::stage_d5_f64(n, rd, lds, sd);
-    case 6: return f32 ? hd::stage_d6_f32(n, rd, lds, sd) : hd::stage_d6_f64(n, rd, lds, sd);
+    case 2: return f32 ? hd::stage_d2_f32(n, rd, lds, sd, opt) : hd::stage_d2_f64(n, rd, lds, sd, opt);
+    case 3: return f32 ? hd::stage_d3_f32(n, rd, lds, sd, opt) : hd::stage_d3_f64(n, rd, lds, sd, opt);
+    case 4: return f32 ? hd::stage_d4_f32(n, rd, lds, sd, opt) : hd::stage_d4_f64(n, rd, lds, sd, opt);
+    case 5: return f32 ? hd::stage_d5_f32(n, rd, lds, sd, opt) : hd::stage_d5_f64(n, rd, lds, sd, opt);
+    case 6: return f32 ? hd::stage_d6_f32(n, rd, lds, sd, opt) : hd::stage_d6_f64(n, rd, lds, sd, opt);
   }
   return nullptr;
 }

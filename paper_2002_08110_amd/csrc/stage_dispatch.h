@@ -42,69 +42,77 @@ constexpr bool split_variant_ok() {
          (size_t)ipow(N, D - SD) * sizeof(P) <= kMaxLdsBytes;
 }
 
-template <int D, int N, int DX, int RD, typename P, bool LDS, int SD = 0>
+template <int D, int N, int DX, int RD, typename P, bool LDS, int SD, int OPT>
 const void *variant_fn() {
   static const void *const f = [] {
-    const void *k = reinterpret_cast<const void *>(&stage_kernel<D, N, DX, RD, P, LDS, SD>);
+    const void *k = reinterpret_cast<const void *>(&stage_kernel<D, N, DX, RD, P, LDS, SD, OPT>);
     return LDS ? allow_max_lds(k, kMaxLdsBytes) : k;
   }();
   return f;
 }
 
+template <int D, int N, int DX, int RD, typename P, bool LDS, int SD>
+const void *resolve_opt(int opt) {
+  return (opt & kOptStream) ? variant_fn<D, N, DX, RD, P, LDS, SD, kOptStream>()
+                            : variant_fn<D, N, DX, RD, P, LDS, SD, 0>();
+}
+
 template <int D, int N, int DX, int RD, typename P>
-const void *resolve_lds(int lds, int sd) {
+const void *resolve_lds(int lds, int sd, int opt) {
   if (sd == 1) {
-    if constexpr (split_variant_ok<D, N, DX, RD, 1, P>()) return lds ? variant_fn<D, N, DX, RD, P, true, 1>() : nullptr;
+    if constexpr (split_variant_ok<D, N, DX, RD, 1, P>())
+      return lds ? resolve_opt<D, N, DX, RD, P, true, 1>(opt) : nullptr;
     return nullptr;
   }
   if (sd == 2) {
-    if constexpr (split_variant_ok<D, N, DX, RD, 2, P>()) return lds ? variant_fn<D, N, DX, RD, P, true, 2>() : nullptr;
+    if constexpr (split_variant_ok<D, N, DX, RD, 2, P>())
+      return lds ? resolve_opt<D, N, DX, RD, P, true, 2>(opt) : nullptr;
     return nullptr;
   }
   if (sd != 0) return nullptr;
   if (lds) {
-    if constexpr (lds_variant_ok<D, N, RD, P>()) return variant_fn<D, N, DX, RD, P, true>();
+    if constexpr (lds_variant_ok<D, N, RD, P>()) return resolve_opt<D, N, DX, RD, P, true, 0>(opt);
     else return nullptr;
   }
-  return variant_fn<D, N, DX, RD, P, false>();
+  return resolve_opt<D, N, DX, RD, P, false, 0>(opt);
 }
 
 template <int D, int N, int DX, typename P>
-const void *resolve_rd(int rd, int lds, int sd) {
+const void *resolve_rd(int rd, int lds, int sd, int opt) {
   constexpr int DV = D - DX;
-  if (rd == 1) return resolve_lds<D, N, DX, 1, P>(lds, sd);
+  if (rd == 1) return resolve_lds<D, N, DX, 1, P>(lds, sd, opt);
   if constexpr (DV >= 2) {
-    if (rd == 2) return resolve_lds<D, N, DX, 2, P>(lds, sd);
+    if (rd == 2) return resolve_lds<D, N, DX, 2, P>(lds, sd, opt);
   }
   return nullptr;
 }
 
 template <int D, int DX, typename P>
-const void *resolve_n(int n, int rd, int lds, int sd) {
+const void *resolve_n(int n, int rd, int lds, int sd, int opt) {
   switch (n) {
-    case 2: return resolve_rd<D, 2, DX, P>(rd, lds, sd);
-    case 3: return resolve_rd<D, 3, DX, P>(rd, lds, sd);
-    case 4: return resolve_rd<D, 4, DX, P>(rd, lds, sd);
-    case 5: return resolve_rd<D, 5, DX, P>(rd, lds, sd);
-    case 6: return resolve_rd<D, 6, DX, P>(rd, lds, sd);
+    case 2: return resolve_rd<D, 2, DX, P>(rd, lds, sd, opt);
+    case 3: return resolve_rd<D, 3, DX, P>(rd, lds, sd, opt);
+    case 4: return resolve_rd<D, 4, DX, P>(rd, lds, sd, opt);
+    case 5: return resolve_rd<D, 5, DX, P>(rd, lds, sd, opt);
+    case 6: return resolve_rd<D, 6, DX, P>(rd, lds, sd, opt);
     default: return nullptr;
   }
 }
 
 // Defined in stage_dN_fP.hip (one per dimension and precision): the entry of
 // the generic kernel for n = degree + 1 nodes per dimension, rd register
-// dims, LDS mode and sd split dims, or nullptr if that variant is not
-// compiled.
-const void *stage_d2_f64(int n, int rd, int lds, int sd);
-const void *stage_d3_f64(int n, int rd, int lds, int sd);
-const void *stage_d4_f64(int n, int rd, int lds, int sd);
-const void *stage_d5_f64(int n, int rd, int lds, int sd);
-const void *stage_d6_f64(int n, int rd, int lds, int sd);
-const void *stage_d2_f32(int n, int rd, int lds, int sd);
-const void *stage_d3_f32(int n, int rd, int lds, int sd);
-const void *stage_d4_f32(int n, int rd, int lds, int sd);
-const void *stage_d5_f32(int n, int rd, int lds, int sd);
-const void *stage_d6_f32(int n, int rd, int lds, int sd);
+// dims, LDS mode, sd split dims and plan options opt, or nullptr if that
+// variant is not compiled.
+const void *stage_d2_f64(int n, int rd, int lds, int sd, int opt);
+const void *stage_d3_f64(int n, int rd, int lds, int sd, int opt);
+const void *stage_d4_f64(int n, int rd, int lds, int sd, int opt);
+const void *stage_d5_f64(int n, int rd, int lds, int sd, int opt);
+const void *stage_d6_f64(int n, int rd, int lds, int sd, int opt);
+const void *stage_d2_f32(int n, int rd, int lds, int sd, int opt);
+const void *stage_d3_f32(int n, int rd, int lds, int sd, int opt);
+const void *stage_d4_f32(int n, int rd, int lds, int sd, int opt);
+const void *stage_d5_f32(int n, int rd, int lds, int sd, int opt);
+const void *stage_d6_f32(int n, int rd, int lds, int sd, int opt);
 
 // Specialised kernel for d = 6 (3 x + 3 v), degree 3: one cell per
 // 256-thread workgroup (stage_k3.hip); options as in hd_plan.

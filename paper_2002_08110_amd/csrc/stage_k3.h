@@ -58,22 +58,11 @@ constexpr int k3_waves_per_eu() {
   return sizeof(P) == 8 ? 2 : 4;
 }
 
-// Plan options (hd_plan.options): bit 0 streams du and the output solution
-// with non-temporal accesses; bit 1 (FP32) keeps the FP64 input solution in
-// registers for the update instead of re-reading it.
-constexpr int kOptStream = 1;
+// Plan options (hd_plan.options): bit 0 (kOptStream, stage_kernel.h)
+// streams du and the output solution with non-temporal accesses; bit 1
+// (FP32) keeps the FP64 input solution in registers for the update instead
+// of re-reading it.
 constexpr int kOptKeepU64 = 2;
-
-template <bool NT, typename T>
-__device__ __forceinline__ T ld_opt(const T *p) {
-  if constexpr (NT) return __builtin_nontemporal_load(p);
-  else return *p;
-}
-template <bool NT, typename T>
-__device__ __forceinline__ void st_opt(T *p, T v) {
-  if constexpr (NT) __builtin_nontemporal_store(v, p);
-  else *p = v;
-}
 
 // One workgroup's cell `cell` (the kernel below and the batched persistent
 // kernel call it; lds_reuse as in stage_body).

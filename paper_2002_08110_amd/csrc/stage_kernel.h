@@ -104,10 +104,26 @@ __device__ __forceinline__ P to_p(double v) {
   return static_cast<P>(v);
 }
 
+// Plan option bit 0: non-temporal (streaming) loads and stores of the stage
+// increment and stores of the output solution, which are not re-read while
+// they could still be cached; keeps the cache for neighbour traces.
+constexpr int kOptStream = 1;
+
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_opt(const T *p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st_opt(T *p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
 // Largest workgroup a variant is launched with: 256 threads, except the LDS
 // variant of units (cells or slabs) with more than 256 pencils, which takes
 // one unit per workgroup (its pencil count, rounded up to whole waves).
-template <int D, int N, int RD, bool USE_LDS, int SD = 0>
+template <int D, int N, int RD, bool USE_LDS, int SD>
 constexpr int stage_max_threads() {
   constexpr int T = ipow(N, D - RD - SD);
   return (USE_LDS && T > 256) ? (T + 63) / 64 * 64 : 256;
@@ -116,8 +132,8 @@ constexpr int stage_max_threads() {
 // One workgroup's share of a stage: the tile `tile` (cells_per_wg units -
 // cells, or slabs of cells if SD > 0 - for the LDS variant; blockDim.x
 // pencils otherwise). lds_reuse: the LDS of a previous tile may still be
-// read by other threads, so wait before overwriting it.
-template <int D, int N, int DX, int RD, typename P, bool USE_LDS, int SD = 0>
+// read by other threads, so wait before overwriting it. OPT: plan options.
+template <int D, int N, int DX, int RD, typename P, bool USE_LDS, int SD, int OPT>
 __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned tile, P *lds,
                                            bool lds_reuse) {
   constexpr int DV = D - DX;
@@ -131,6 +147,10 @@ __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned t
   constexpr int SST = ipow(N, NF + SD);  // node stride of the first register dim
   constexpr int UN = T * NS;          // nodes per unit
   static_assert(DX <= NF, "all x dims are thread-distributed");
+  constexpr bool NT = (OPT & kOptStream) != 0;
+  // FP32 mode keeps the FP64 input for the update when a thread owns few
+  // nodes (else it is re-read: registers are scarce).
+  constexpr bool KEEPU = sizeof(P) == 4 && NS <= 8;
 
   unsigned cell, f, lc = 0, unit = 0;
   if constexpr (USE_LDS) {
@@ -182,8 +202,13 @@ __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned t
 
   const uint64_t base = (uint64_t)cl * ND + f + soff;
   P u[NS];
+  double u64[KEEPU ? NS : 1];
 #pragma unroll
-  for (int s = 0; s < NS; ++s) u[s] = to_p<P>(prm.u_in[base + (uint64_t)s * SST]);
+  for (int s = 0; s < NS; ++s) {
+    const double x = prm.u_in[base + (uint64_t)s * SST];
+    if constexpr (KEEPU) u64[s] = x;
+    u[s] = to_p<P>(x);
+  }
   const bool stage = prm.mode == 1;
   if constexpr (USE_LDS) {
     if (lds_reuse) __syncthreads();
@@ -272,7 +297,7 @@ __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned t
   P dv[NS];
   if (kPrefetchDu && stage && prm.read_du) {
 #pragma unroll
-    for (int s = 0; s < NS; ++s) dv[s] = prm.du[base + (uint64_t)s * SST];
+    for (int s = 0; s < NS; ++s) dv[s] = ld_opt<NT>(prm.du + base + (uint64_t)s * SST);
   }
   sched_fence();
 
@@ -413,7 +438,7 @@ __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned t
   if (prm.read_du) {
     if (!kPrefetchDu) {
 #pragma unroll
-      for (int s = 0; s < NS; ++s) dv[s] = prm.du[base + (uint64_t)s * SST];
+      for (int s = 0; s < NS; ++s) dv[s] = ld_opt<NT>(prm.du + base + (uint64_t)s * SST);
     }
 #pragma unroll
     for (int s = 0; s < NS; ++s) dv[s] = prm.rk_a * dv[s] + prm.dt * acc[s];
@@ -423,23 +448,26 @@ __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned t
   }
   if (prm.write_du) {
 #pragma unroll
-    for (int s = 0; s < NS; ++s) prm.du[base + (uint64_t)s * SST] = dv[s];
+    for (int s = 0; s < NS; ++s) st_opt<NT>(prm.du + base + (uint64_t)s * SST, dv[s]);
   }
-  // FP64 solution update; in FP32 mode the FP64 input is re-read (cache hit).
+  // FP64 solution update (FP32 mode: the kept or re-read FP64 input).
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    const double uo = sizeof(P) == sizeof(double) ? (double)u[s] : prm.u_in[base + (uint64_t)s * SST];
-    prm.u_out[base + (uint64_t)s * SST] = uo + prm.rk_b * (double)dv[s];
+    double uo;
+    if constexpr (sizeof(P) == sizeof(double)) uo = (double)u[s];
+    else if constexpr (KEEPU) uo = u64[s];
+    else uo = prm.u_in[base + (uint64_t)s * SST];
+    st_opt<NT>(prm.u_out + base + (uint64_t)s * SST, uo + prm.rk_b * (double)dv[s]);
   }
 }
 
-template <int D, int N, int DX, int RD, typename P, bool USE_LDS, int SD = 0>
+template <int D, int N, int DX, int RD, typename P, bool USE_LDS, int SD, int OPT>
 __global__ void __launch_bounds__((stage_max_threads<D, N, RD, USE_LDS, SD>()))
     stage_kernel(const StageParams<P> prm) {
   extern __shared__ unsigned char smem_raw[];
   unsigned tile = blockIdx.x;
   if (prm.xcd_remap) tile = xcd_tile(tile, prm.nblocks);
-  stage_body<D, N, DX, RD, P, USE_LDS, SD>(prm, tile, reinterpret_cast<P *>(smem_raw), false);
+  stage_body<D, N, DX, RD, P, USE_LDS, SD, OPT>(prm, tile, reinterpret_cast<P *>(smem_raw), false);
 }
 
 }  // namespace hd

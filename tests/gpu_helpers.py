@@ -60,7 +60,8 @@ def x_table_size(case: W.Case):
 
 
 def all_plans(case: W.Case, precision="fp64"):
-    """Every valid launch plan of the stage kernel for this case."""
+    """Every valid launch plan of the stage kernel for this case (the generic
+    kernel's streaming option alternates over the plans)."""
     n = case.degree + 1
     d = case.d
     psize = 4 if precision == "fp32" else 8
@@ -89,6 +90,8 @@ def all_plans(case: W.Case, precision="fp64"):
                     if cpw * nd * psize <= 160 * 1024:
                         plans.append(dict(lds=1, cells_per_wg=cpw, reg_dims=rd, xcd_remap=xcd,
                                           wg_size=256, kernel=0, split_dims=0))
+    for i, p in enumerate(plans):
+        p["options"] = i % 2
     if k3_eligible(case):
         for xcd in (0, 1):
             for opt in range(4):
