@@ -95,7 +95,11 @@ typedef struct hd_batch hd_batch;    /* opaque */
  *              of one node layer each; a workgroup stages one slab in LDS and
  *              reads the other slabs of the line from global memory. 0, 1 or
  *              2; compiled for degree >= 4 at d >= 5, for cells too large to
- *              stage whole. */
+ *              stage whole.
+ *  loop_dims:  (kernel 0, lds = 1, cells_per_wg = 1) 1 = a thread covers the
+ *              k+1 pencils that differ in the slowest thread-distributed
+ *              dimension one after another, so units of more than 1024
+ *              pencils fit a workgroup; compiled for degree >= 4 at d >= 5. */
 typedef struct {
   int lds;
   int cells_per_wg;
@@ -105,6 +109,7 @@ typedef struct {
   int kernel;
   int options;
   int split_dims;
+  int loop_dims;
 } hd_plan;
 
 /* Create a solver for `mesh` and polynomial degree `degree` (k+1 nodes per

@@ -40,7 +40,8 @@ class hd_plan(ctypes.Structure):
     _fields_ = [("lds", ctypes.c_int), ("cells_per_wg", ctypes.c_int),
                 ("wg_size", ctypes.c_int), ("xcd_remap", ctypes.c_int),
                 ("reg_dims", ctypes.c_int), ("kernel", ctypes.c_int),
-                ("options", ctypes.c_int), ("split_dims", ctypes.c_int)]
+                ("options", ctypes.c_int), ("split_dims", ctypes.c_int),
+                ("loop_dims", ctypes.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

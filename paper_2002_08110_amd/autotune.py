@@ -58,6 +58,15 @@ def candidate_plans(d, k, dim_v, precision):
                     for xcd in (0, 1):
                         plans.append(dict(kernel=0, options=0, lds=1, cells_per_wg=cpw, reg_dims=rd,
                                           split_dims=sd, xcd_remap=xcd, wg_size=256))
+        for sd in (0, 1, 2):
+            # looped pencils: a thread covers the k+1 pencils of one fast dim
+            nf = d - rd - sd
+            if (n < 5 or d < 5 or rd + sd > dim_v or nf - 1 < d - dim_v
+                    or n ** (nf - 1) > 1024 or n ** (d - sd) * psize > 160 * 1024):
+                continue
+            for xcd in (0, 1):
+                plans.append(dict(kernel=0, options=0, lds=1, cells_per_wg=1, reg_dims=rd,
+                                  split_dims=sd, loop_dims=1, xcd_remap=xcd, wg_size=256))
         T = n ** (d - rd)
         for xcd in (0, 1):
             plans.append(dict(kernel=0, options=0, lds=0, wg_size=256, reg_dims=rd, xcd_remap=xcd,
@@ -71,7 +80,21 @@ def candidate_plans(d, k, dim_v, precision):
     generic = [p for p in plans if p["kernel"] == 0]
     for p in generic:  # the streaming option of the generic kernel
         plans.append(dict(p, options=1))
-    return plans
+    full = dict(lds=0, cells_per_wg=1, wg_size=256, xcd_remap=0, reg_dims=1, kernel=0, options=0,
+                split_dims=0, loop_dims=0)
+    return [dict(full, **p) for p in plans]
+
+
+def same_launch(a, b):
+    """True if two plans launch the same kernel the same way (fields that
+    the chosen kernel ignores do not count)."""
+    if a.get("kernel", 0) != b.get("kernel", 0):
+        return False
+    keys = ["xcd_remap", "options"]
+    if a.get("kernel", 0) == 0:
+        keys += ["lds", "reg_dims", "split_dims", "loop_dims"]
+        keys += ["cells_per_wg"] if a.get("lds") else ["wg_size"]
+    return all(a.get(k, 0) == b.get(k, 0) for k in keys)
 
 
 def representative_case(d, k, target_dofs=1.5e8):

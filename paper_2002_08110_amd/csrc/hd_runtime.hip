@@ -9,7 +9,9 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <mutex>
 #include <string>
+#include <unordered_set>
 #include <vector>
 
 #include "hd_internal.h"
@@ -75,7 +77,7 @@ bool valid_plan(const hd_solver *s, const hd_plan &p, std::string *why) {
     }
     return true;
   }
-  const int rd = p.reg_dims, sd = p.split_dims;
+  const int rd = p.reg_dims, sd = p.split_dims, ld = p.loop_dims;
   if (rd < 1 || rd > 2 || rd > s->dv) {
     *why = "reg_dims must be 1 or 2 and at most dim_v";
     return false;
@@ -85,8 +87,12 @@ bool valid_plan(const hd_solver *s, const hd_plan &p, std::string *why) {
            "degree >= 4 and d >= 5";
     return false;
   }
+  if (ld < 0 || ld > 1 || (ld == 1 && (!p.lds || p.cells_per_wg != 1))) {
+    *why = "loop_dims must be 0 or 1; 1 needs lds = 1 and cells_per_wg = 1";
+    return false;
+  }
   int64_t T = 1, unit = 1;  // threads and nodes of one unit (cell or slab)
-  for (int j = 0; j < s->d - rd - sd; ++j) T *= s->n;
+  for (int j = 0; j < s->d - rd - sd - ld; ++j) T *= s->n;
   for (int j = 0; j < s->d - sd; ++j) unit *= s->n;
   if (p.lds) {
     const int64_t unit_bytes = unit * (int64_t)s->psize();
@@ -109,6 +115,17 @@ bool valid_plan(const hd_solver *s, const hd_plan &p, std::string *why) {
       return false;
     }
   }
+  // The variant must be compiled.
+  hd_solver probe;
+  probe.d = s->d;
+  probe.dx = s->dx;
+  probe.n = s->n;
+  probe.prec = s->prec;
+  probe.plan = p;
+  if (!hd::rt::stage_entry(&probe)) {
+    *why = "no compiled kernel variant for this plan";
+    return false;
+  }
   return true;
 }
 
@@ -120,31 +137,34 @@ hd_plan default_plan(const hd_solver *s) {
   // (16 nodes per thread), FP32 one.
   p.reg_dims = (s->dv >= 2 && (s->n <= 3 || (s->n == 4 && s->prec == HD_FP64))) ? 2 : 1;
   // Cells too large for LDS at degree 5 (d = 5, 6), and 6D degree 4 in
-  // FP64: slabs along one or two velocity dimensions (measured on MI355X).
+  // FP64: slabs along a velocity dimension and/or threads that loop over
+  // the pencils of the first velocity dimension (measured on MI355X).
   if (s->n == 6 && s->d == 6) {
     p.reg_dims = 1;
-    p.split_dims = 2;
+    p.split_dims = 1;
+    p.loop_dims = 1;
   } else if (s->n == 6 && s->d == 5) {
     p.reg_dims = 1;
-    p.split_dims = 1;
+    p.loop_dims = 1;
   } else if (s->n == 5 && s->d == 6 && s->prec == HD_FP64) {
     p.reg_dims = 2;
     p.split_dims = 1;
   } else if (s->n == 5 && s->d == 6) {
     p.reg_dims = 2;
   }
-  int64_t T = 1, unit = 1;
-  for (int j = 0; j < s->d - p.reg_dims - p.split_dims; ++j) T *= s->n;
+  int64_t T = 1, unit = 1;  // threads and nodes of one unit
+  for (int j = 0; j < s->d - p.reg_dims - p.split_dims - p.loop_dims; ++j) T *= s->n;
   for (int j = 0; j < s->d - p.split_dims; ++j) unit *= s->n;
   const int64_t unit_bytes = unit * (int64_t)s->psize();
   if (T <= 1024 && unit_bytes <= (int64_t)hd::kMaxLdsBytes) {
     p.lds = 1;
-    int cpw = T <= 256 ? (int)(256 / T) : 1;
+    int cpw = (T <= 256 && !p.loop_dims) ? (int)(256 / T) : 1;
     while (cpw > 1 && cpw * unit_bytes > (int64_t)hd::kMaxLdsBytes) --cpw;
     p.cells_per_wg = std::max(1, cpw);
   } else {
     p.lds = 0;
     p.split_dims = 0;
+    p.loop_dims = 0;
     p.cells_per_wg = 1;
   }
   p.kernel = k3_eligible(s) ? 1 : 0;
@@ -169,7 +189,7 @@ hd::LaunchShape hd::rt::shape_of(const hd_solver *s) {
   }
   const int sd = s->plan.split_dims;
   int64_t T = 1, per_cell = 1;  // threads per unit, units per cell
-  for (int j = 0; j < s->d - s->plan.reg_dims - sd; ++j) T *= s->n;
+  for (int j = 0; j < s->d - s->plan.reg_dims - sd - s->plan.loop_dims; ++j) T *= s->n;
   for (int j = 0; j < sd; ++j) per_cell *= s->n;
   if (s->plan.lds) {
     const int64_t cpw = s->plan.cells_per_wg;
@@ -194,13 +214,13 @@ const void *stage_entry(const hd_solver *s) {
   if (s->plan.kernel == 1) return f32 ? hd::stage_k3_f32(s->plan.options)
                                       : hd::stage_k3_f64(s->plan.options);
   const int rd = s->plan.reg_dims, lds = s->plan.lds, n = s->n, sd = s->plan.split_dims,
-            opt = s->plan.options;
+            opt = s->plan.options, ld = s->plan.loop_dims;
   switch (s->d) {
-    case 2: return f32 ? hd::stage_d2_f32(n, rd, lds, sd, opt) : hd::stage_d2_f64(n, rd, lds, sd, opt);
-    case 3: return f32 ? hd::stage_d3_f32(n, rd, lds, sd, opt) : hd::stage_d3_f64(n, rd, lds, sd, opt);
-    case 4: return f32 ? hd::stage_d4_f32(n, rd, lds, sd, opt) : hd::stage_d4_f64(n, rd, lds, sd, opt);
-    case 5: return f32 ? hd::stage_d5_f32(n, rd, lds, sd, opt) : hd::stage_d5_f64(n, rd, lds, sd, opt);
-    case 6: return f32 ? hd::stage_d6_f32(n, rd, lds, sd, opt) : hd::stage_d6_f64(n, rd, lds, sd, opt);
+    case 2: return f32 ? hd::stage_d2_f32(n, rd, lds, sd, opt, ld) : hd::stage_d2_f64(n, rd, lds, sd, opt, ld);
+    case 3: return f32 ? hd::stage_d3_f32(n, rd, lds, sd, opt, ld) : hd::stage_d3_f64(n, rd, lds, sd, opt, ld);
+    case 4: return f32 ? hd::stage_d4_f32(n, rd, lds, sd, opt, ld) : hd::stage_d4_f64(n, rd, lds, sd, opt, ld);
+    case 5: return f32 ? hd::stage_d5_f32(n, rd, lds, sd, opt, ld) : hd::stage_d5_f64(n, rd, lds, sd, opt, ld);
+    case 6: return f32 ? hd::stage_d6_f32(n, rd, lds, sd, opt, ld) : hd::stage_d6_f64(n, rd, lds, sd, opt, ld);
   }
   return nullptr;
 }
@@ -215,6 +235,18 @@ namespace {
 bool split_compiled(int dx, int dv) {
   return (dx == 1 && dv == 1) || (dx == 2 && dv == 1) || (dx == 2 && dv == 2) ||
          (dx == 3 && dv == 2) || (dx == 3 && dv == 3);
+}
+
+// Lets a kernel use up to 160 KiB of dynamic LDS, once per kernel entry.
+hipError_t allow_large_lds(const void *fn) {
+  static std::mutex mu;
+  static std::unordered_set<const void *> done;
+  std::lock_guard<std::mutex> lock(mu);
+  if (done.count(fn)) return hipSuccess;
+  hipError_t e =
+      hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)hd::kMaxLdsBytes);
+  if (e == hipSuccess) done.insert(fn);
+  return e;
 }
 
 template <typename P>
@@ -243,6 +275,11 @@ hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, in
                                     "nodes per thread");
   const void *fn = hd::rt::stage_entry(s);
   if (!fn) return fail(HD_ERR_HIP, "no compiled stage kernel for this plan");
+  if (ls.shmem > 65536) {
+    hipError_t ae = allow_large_lds(fn);
+    if (ae != hipSuccess)
+      return fail(HD_ERR_HIP, std::string("raising the LDS limit: ") + hipGetErrorString(ae));
+  }
   void *args[] = {&prm};
   hipError_t e = hipLaunchKernel(fn, dim3(ls.grid), dim3(ls.block), args, ls.shmem, st);
   if (e != hipSuccess) return fail(HD_ERR_HIP, std::string("stage kernel launch: ") + hipGetErrorString(e));

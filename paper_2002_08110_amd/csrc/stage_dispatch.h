@@ -3,7 +3,8 @@
 // stage_dN.hip translation unit instantiates the kernels of one dimension d
 // (all degrees, both precisions, both LDS modes, the valid register-dim
 // counts) so the instantiations compile in parallel. The caller launches the
-// returned entry with hipLaunchKernel.
+// returned entry with hipLaunchKernel (after raising its dynamic-LDS limit
+// when a launch needs more than 64 KiB). Resolution makes no HIP call.
 #pragma once
 
 #include "stage_kernel.h"
@@ -17,14 +18,6 @@ struct LaunchShape {
   size_t shmem;
 };
 
-// Lets a kernel use the whole LDS of a workgroup; the entry, or nullptr if
-// the runtime refuses.
-inline const void *allow_max_lds(const void *fn, size_t bytes) {
-  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
-                 hipSuccess
-             ? fn
-             : nullptr;
-}
 
 // True if the LDS variant of (D, N, RD, P) can hold at least one cell.
 template <int D, int N, int RD, typename P>
@@ -42,23 +35,44 @@ constexpr bool split_variant_ok() {
          (size_t)ipow(N, D - SD) * sizeof(P) <= kMaxLdsBytes;
 }
 
-template <int D, int N, int DX, int RD, typename P, bool LDS, int SD, int OPT>
-const void *variant_fn() {
-  static const void *const f = [] {
-    const void *k = reinterpret_cast<const void *>(&stage_kernel<D, N, DX, RD, P, LDS, SD, OPT>);
-    return LDS ? allow_max_lds(k, kMaxLdsBytes) : k;
-  }();
-  return f;
+// True if the looped variant (a thread covers the N pencils of the slowest
+// fast dimension) of (D, N, RD, SD, P) is compiled: units of more than 1024
+// pencils at degree >= 4, d >= 5, that fit LDS; the looped dimension is a
+// velocity dimension.
+template <int D, int N, int DX, int RD, int SD, typename P>
+constexpr bool loop_variant_ok() {
+  return N >= 5 && D >= 5 && RD + SD <= D - DX && D - RD - SD >= DX + 1 &&
+         ipow(N, D - RD - SD - 1) <= 1024 &&
+         (size_t)ipow(N, D - SD) * sizeof(P) <= kMaxLdsBytes;
 }
 
-template <int D, int N, int DX, int RD, typename P, bool LDS, int SD>
+template <int D, int N, int DX, int RD, typename P, bool LDS, int SD, int OPT, int LD>
+const void *variant_fn() {
+  return reinterpret_cast<const void *>(&stage_kernel<D, N, DX, RD, P, LDS, SD, OPT, LD>);
+}
+
+template <int D, int N, int DX, int RD, typename P, bool LDS, int SD, int LD = 0>
 const void *resolve_opt(int opt) {
-  return (opt & kOptStream) ? variant_fn<D, N, DX, RD, P, LDS, SD, kOptStream>()
-                            : variant_fn<D, N, DX, RD, P, LDS, SD, 0>();
+  return (opt & kOptStream) ? variant_fn<D, N, DX, RD, P, LDS, SD, kOptStream, LD>()
+                            : variant_fn<D, N, DX, RD, P, LDS, SD, 0, LD>();
+}
+
+template <int D, int N, int DX, int RD, typename P, int SD>
+const void *resolve_loop(int lds, int opt) {
+  if constexpr (loop_variant_ok<D, N, DX, RD, SD, P>())
+    return lds ? resolve_opt<D, N, DX, RD, P, true, SD, 1>(opt) : nullptr;
+  return nullptr;
 }
 
 template <int D, int N, int DX, int RD, typename P>
-const void *resolve_lds(int lds, int sd, int opt) {
+const void *resolve_lds(int lds, int sd, int opt, int ld) {
+  if (ld == 1) {
+    if (sd == 0) return resolve_loop<D, N, DX, RD, P, 0>(lds, opt);
+    if (sd == 1) return resolve_loop<D, N, DX, RD, P, 1>(lds, opt);
+    if (sd == 2) return resolve_loop<D, N, DX, RD, P, 2>(lds, opt);
+    return nullptr;
+  }
+  if (ld != 0) return nullptr;
   if (sd == 1) {
     if constexpr (split_variant_ok<D, N, DX, RD, 1, P>())
       return lds ? resolve_opt<D, N, DX, RD, P, true, 1>(opt) : nullptr;
@@ -78,41 +92,41 @@ const void *resolve_lds(int lds, int sd, int opt) {
 }
 
 template <int D, int N, int DX, typename P>
-const void *resolve_rd(int rd, int lds, int sd, int opt) {
+const void *resolve_rd(int rd, int lds, int sd, int opt, int ld) {
   constexpr int DV = D - DX;
-  if (rd == 1) return resolve_lds<D, N, DX, 1, P>(lds, sd, opt);
+  if (rd == 1) return resolve_lds<D, N, DX, 1, P>(lds, sd, opt, ld);
   if constexpr (DV >= 2) {
-    if (rd == 2) return resolve_lds<D, N, DX, 2, P>(lds, sd, opt);
+    if (rd == 2) return resolve_lds<D, N, DX, 2, P>(lds, sd, opt, ld);
   }
   return nullptr;
 }
 
 template <int D, int DX, typename P>
-const void *resolve_n(int n, int rd, int lds, int sd, int opt) {
+const void *resolve_n(int n, int rd, int lds, int sd, int opt, int ld) {
   switch (n) {
-    case 2: return resolve_rd<D, 2, DX, P>(rd, lds, sd, opt);
-    case 3: return resolve_rd<D, 3, DX, P>(rd, lds, sd, opt);
-    case 4: return resolve_rd<D, 4, DX, P>(rd, lds, sd, opt);
-    case 5: return resolve_rd<D, 5, DX, P>(rd, lds, sd, opt);
-    case 6: return resolve_rd<D, 6, DX, P>(rd, lds, sd, opt);
+    case 2: return resolve_rd<D, 2, DX, P>(rd, lds, sd, opt, ld);
+    case 3: return resolve_rd<D, 3, DX, P>(rd, lds, sd, opt, ld);
+    case 4: return resolve_rd<D, 4, DX, P>(rd, lds, sd, opt, ld);
+    case 5: return resolve_rd<D, 5, DX, P>(rd, lds, sd, opt, ld);
+    case 6: return resolve_rd<D, 6, DX, P>(rd, lds, sd, opt, ld);
     default: return nullptr;
   }
 }
 
 // Defined in stage_dN_fP.hip (one per dimension and precision): the entry of
 // the generic kernel for n = degree + 1 nodes per dimension, rd register
-// dims, LDS mode, sd split dims and plan options opt, or nullptr if that
-// variant is not compiled.
-const void *stage_d2_f64(int n, int rd, int lds, int sd, int opt);
-const void *stage_d3_f64(int n, int rd, int lds, int sd, int opt);
-const void *stage_d4_f64(int n, int rd, int lds, int sd, int opt);
-const void *stage_d5_f64(int n, int rd, int lds, int sd, int opt);
-const void *stage_d6_f64(int n, int rd, int lds, int sd, int opt);
-const void *stage_d2_f32(int n, int rd, int lds, int sd, int opt);
-const void *stage_d3_f32(int n, int rd, int lds, int sd, int opt);
-const void *stage_d4_f32(int n, int rd, int lds, int sd, int opt);
-const void *stage_d5_f32(int n, int rd, int lds, int sd, int opt);
-const void *stage_d6_f32(int n, int rd, int lds, int sd, int opt);
+// dims, LDS mode, sd split dims, plan options opt and ld looped dims, or
+// nullptr if that variant is not compiled.
+const void *stage_d2_f64(int n, int rd, int lds, int sd, int opt, int ld);
+const void *stage_d3_f64(int n, int rd, int lds, int sd, int opt, int ld);
+const void *stage_d4_f64(int n, int rd, int lds, int sd, int opt, int ld);
+const void *stage_d5_f64(int n, int rd, int lds, int sd, int opt, int ld);
+const void *stage_d6_f64(int n, int rd, int lds, int sd, int opt, int ld);
+const void *stage_d2_f32(int n, int rd, int lds, int sd, int opt, int ld);
+const void *stage_d3_f32(int n, int rd, int lds, int sd, int opt, int ld);
+const void *stage_d4_f32(int n, int rd, int lds, int sd, int opt, int ld);
+const void *stage_d5_f32(int n, int rd, int lds, int sd, int opt, int ld);
+const void *stage_d6_f32(int n, int rd, int lds, int sd, int opt, int ld);
 
 // Specialised kernel for d = 6 (3 x + 3 v), degree 3: one cell per
 // 256-thread workgroup (stage_k3.hip); options as in hd_plan.

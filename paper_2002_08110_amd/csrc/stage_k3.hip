@@ -6,9 +6,7 @@ namespace hd {
 
 template <typename P, int OPT>
 static const void *k3_fn() {
-  static const void *const f =
-      allow_max_lds(reinterpret_cast<const void *>(&stage_k3_kernel<P, OPT>), k3_lds_bytes<P>());
-  return f;
+  return reinterpret_cast<const void *>(&stage_k3_kernel<P, OPT>);
 }
 
 const void *stage_k3_f64(int options) {

@@ -123,9 +123,9 @@ __device__ __forceinline__ void st_opt(T *p, T v) {
 // Largest workgroup a variant is launched with: 256 threads, except the LDS
 // variant of units (cells or slabs) with more than 256 pencils, which takes
 // one unit per workgroup (its pencil count, rounded up to whole waves).
-template <int D, int N, int RD, bool USE_LDS, int SD>
+template <int D, int N, int RD, bool USE_LDS, int SD, int LD = 0>
 constexpr int stage_max_threads() {
-  constexpr int T = ipow(N, D - RD - SD);
+  constexpr int T = ipow(N, D - RD - SD - LD);
   return (USE_LDS && T > 256) ? (T + 63) / 64 * 64 : 256;
 }
 
@@ -133,36 +133,43 @@ constexpr int stage_max_threads() {
 // cells, or slabs of cells if SD > 0 - for the LDS variant; blockDim.x
 // pencils otherwise). lds_reuse: the LDS of a previous tile may still be
 // read by other threads, so wait before overwriting it. OPT: plan options.
-template <int D, int N, int DX, int RD, typename P, bool USE_LDS, int SD, int OPT>
+// LD = 1 (LDS variant): a thread covers the N pencils that differ in the
+// slowest fast dimension one after another, so a unit of N^NF pencils runs
+// on N^(NF-1) threads: large units fit a workgroup, and the sweep along that
+// dimension still reads LDS.
+template <int D, int N, int DX, int RD, typename P, bool USE_LDS, int SD, int OPT, int LD = 0>
 __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned tile, P *lds,
                                            bool lds_reuse) {
   constexpr int DV = D - DX;
   static_assert(RD >= 1 && RD + SD <= DV, "register and split dims must be velocity dims");
   static_assert(SD == 0 || USE_LDS, "split dims need the LDS variant");
-  constexpr int NF = D - RD - SD;     // thread-distributed (fast) dims
+  static_assert(LD == 0 || (LD == 1 && USE_LDS), "looped pencils need the LDS variant");
+  constexpr int NF = D - RD - SD;     // fast (pencil-indexing) dims
   constexpr int ND = ipow(N, D);      // nodes per cell
-  constexpr int T = ipow(N, NF);      // threads per unit
-  constexpr int NS = ipow(N, RD);     // nodes per thread
+  constexpr int T = ipow(N, NF);      // pencils per unit
+  constexpr int CL = ipow(N, LD);     // pencils per thread
+  constexpr int TT = T / CL;          // threads per unit
+  constexpr int NS = ipow(N, RD);     // nodes per pencil
   constexpr int NU = ipow(N, SD);     // units (slabs) per cell
   constexpr int SST = ipow(N, NF + SD);  // node stride of the first register dim
   constexpr int UN = T * NS;          // nodes per unit
-  static_assert(DX <= NF, "all x dims are thread-distributed");
+  static_assert(DX <= NF, "all x dims are fast dims");
   constexpr bool NT = (OPT & kOptStream) != 0;
   // FP32 mode keeps the FP64 input for the update when a thread owns few
   // nodes (else it is re-read: registers are scarce).
-  constexpr bool KEEPU = sizeof(P) == 4 && NS <= 8;
+  constexpr bool KEEPU = sizeof(P) == 4 && NS <= 8 && LD == 0;
 
-  unsigned cell, f, lc = 0, unit = 0;
+  unsigned cell, t0, lc = 0, unit = 0;
   if constexpr (USE_LDS) {
-    lc = threadIdx.x / T;
-    f = threadIdx.x - lc * T;
+    lc = threadIdx.x / TT;
+    t0 = threadIdx.x - lc * TT;
     const unsigned U = tile * prm.cells_per_wg + lc;
     cell = U / NU;
     unit = U - cell * NU;
   } else {
     const uint64_t p = (uint64_t)tile * blockDim.x + threadIdx.x;
     cell = (unsigned)(p / T);
-    f = (unsigned)(p - (uint64_t)cell * T);
+    t0 = (unsigned)(p - (uint64_t)cell * T);
   }
   // (A workgroup wider than cells_per_wg * T - the batched kernel's fixed
   // 256 threads - leaves the extra threads inactive.)
@@ -176,16 +183,16 @@ __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned t
   unsigned c[D];
 #pragma unroll
   for (int j = 0; j < D; ++j) c[j] = (cl / prm.cstride[j]) % prm.cells[j];
-  // Fast node digits of this thread.
-  int fd[NF > 0 ? NF : 1];
-  {
-    unsigned r = f;
+  // Fast node digits of pencil f.
+  auto digits = [&](unsigned f, int *fd) __attribute__((always_inline)) {
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
-      fd[j] = (int)(r % N);
-      r /= N;
+      fd[j] = (int)(f % N);
+      f /= N;
     }
-  }
+  };
+  int fd0[NF > 0 ? NF : 1];
+  if constexpr (LD == 0) digits(t0, fd0);
 
   // Split digits of this unit and the unit's node offset in the cell.
   int sd[SD > 0 ? SD : 1];
@@ -200,24 +207,49 @@ __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned t
     }
   }
 
-  const uint64_t base = (uint64_t)cl * ND + f + soff;
+  const uint64_t base0 = (uint64_t)cl * ND + t0 + soff;
   P u[NS];
   double u64[KEEPU ? NS : 1];
+  if constexpr (LD == 0) {
+    const uint64_t base = base0;
 #pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const double x = prm.u_in[base + (uint64_t)s * SST];
-    if constexpr (KEEPU) u64[s] = x;
-    u[s] = to_p<P>(x);
+    for (int s = 0; s < NS; ++s) {
+      const double x = prm.u_in[base + (uint64_t)s * SST];
+      if constexpr (KEEPU) u64[s] = x;
+      u[s] = to_p<P>(x);
+    }
   }
   const bool stage = prm.mode == 1;
   if constexpr (USE_LDS) {
-    if (lds_reuse) __syncthreads();
-    if (active) {
+    if constexpr (LD == 0) {
+      if (lds_reuse) __syncthreads();
+      if (active) {
 #pragma unroll
-      for (int s = 0; s < NS; ++s) lds[lc * UN + f + s * T] = u[s];
+        for (int s = 0; s < NS; ++s) lds[lc * UN + t0 + s * T] = u[s];
+      }
+    } else {
+      // All pencils of this thread (the compiler issues loads ahead of the
+      // stores as far as registers allow).
+      const uint64_t base = (uint64_t)cl * ND + t0 + soff;
+      if (lds_reuse) __syncthreads();
+      if (active) {
+#pragma unroll
+        for (int q = 0; q < CL; ++q)
+#pragma unroll
+          for (int s = 0; s < NS; ++s)
+            lds[lc * UN + t0 + q * TT + s * T] = to_p<P>(prm.u_in[base + q * TT + (uint64_t)s * SST]);
+      }
     }
     __syncthreads();
     if (!active) return;
+  }
+
+  // The pencil f of this thread: field, sweeps, faces, update.
+  auto pencil = [&](const unsigned f, const int *fd, const uint64_t base)
+                    __attribute__((always_inline)) {
+  if constexpr (LD == 1) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) u[s] = lds[lc * UN + f + s * T];
   }
 
   // Field at this thread's nodes. x dims are all fast, so E is per thread.
@@ -459,15 +491,27 @@ __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned t
     else uo = prm.u_in[base + (uint64_t)s * SST];
     st_opt<NT>(prm.u_out + base + (uint64_t)s * SST, uo + prm.rk_b * (double)dv[s]);
   }
+  };  // pencil
+  if constexpr (LD == 0) {
+    pencil(t0, fd0, base0);
+  } else {
+#pragma unroll 1
+    for (int q = 0; q < CL; ++q) {
+      int fd[NF > 0 ? NF : 1];
+      digits(t0 + q * TT, fd);
+      pencil(t0 + q * TT, fd, base0 + q * TT);
+    }
+  }
 }
 
-template <int D, int N, int DX, int RD, typename P, bool USE_LDS, int SD, int OPT>
-__global__ void __launch_bounds__((stage_max_threads<D, N, RD, USE_LDS, SD>()))
+template <int D, int N, int DX, int RD, typename P, bool USE_LDS, int SD, int OPT, int LD = 0>
+__global__ void __launch_bounds__((stage_max_threads<D, N, RD, USE_LDS, SD, LD>()))
     stage_kernel(const StageParams<P> prm) {
   extern __shared__ unsigned char smem_raw[];
   unsigned tile = blockIdx.x;
   if (prm.xcd_remap) tile = xcd_tile(tile, prm.nblocks);
-  stage_body<D, N, DX, RD, P, USE_LDS, SD, OPT>(prm, tile, reinterpret_cast<P *>(smem_raw), false);
+  stage_body<D, N, DX, RD, P, USE_LDS, SD, OPT, LD>(prm, tile, reinterpret_cast<P *>(smem_raw),
+                                                    false);
 }
 
 }  // namespace hd

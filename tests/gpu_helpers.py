@@ -79,6 +79,13 @@ def all_plans(case: W.Case, precision="fp64"):
                 if cpw * ub <= 160 * 1024:
                     plans.append(dict(lds=1, cells_per_wg=cpw, reg_dims=rd, split_dims=sd,
                                       xcd_remap=cpw % 2, wg_size=256, kernel=0))
+        for sd in (0, 1, 2):  # looped-pencil variants (degree >= 4, d >= 5)
+            nf = d - rd - sd
+            if (n < 5 or d < 5 or rd + sd > case.dim_v or nf - 1 < case.dim_x
+                    or n ** (nf - 1) > 1024 or n ** (d - sd) * psize > 160 * 1024):
+                continue
+            plans.append(dict(lds=1, cells_per_wg=1, reg_dims=rd, split_dims=sd, loop_dims=1,
+                              xcd_remap=sd % 2, wg_size=256, kernel=0))
         T = n ** (d - rd)
         for xcd in (0, 1):
             for wg in (64, 256):
@@ -96,7 +103,9 @@ def all_plans(case: W.Case, precision="fp64"):
         for xcd in (0, 1):
             for opt in range(4):
                 plans.append(dict(kernel=1, xcd_remap=xcd, reg_dims=2, options=opt, split_dims=0))
-    return plans
+    full = dict(lds=0, cells_per_wg=1, wg_size=256, xcd_remap=0, reg_dims=1, kernel=0, options=0,
+                split_dims=0, loop_dims=0)
+    return [dict(full, **p) for p in plans]
 
 
 def k3_eligible(case: W.Case):

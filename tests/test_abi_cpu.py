@@ -121,7 +121,7 @@ def test_autotune_candidates_are_valid_plans(d, k, precision):
     for plan in plans:
         S.set_plan(**plan)
     S.close()
-    assert any(all(default[key] == v for key, v in p.items()) for p in plans) or d == 6 and k == 5
+    assert any(autotune.same_launch(default, p) for p in plans)
 
 
 def test_autotune_cache_lookup(tmp_path):

@@ -69,12 +69,13 @@ def test_apply_matches_oracle_fp64(d, k, field):
         out = S.apply(ut).cpu().numpy()
         assert rel_l2(out, ref) <= TOL_FP64, plan
         assert rel_max(out, ref) <= TOL_FP64, plan
-        outs.setdefault((plan.get("kernel", 0), plan["reg_dims"]), []).append(out)
-    # Plans of one kernel with the same register dims evaluate each output
-    # with the same
-    # arithmetic whatever the schedule (LDS or global reads, cells per
-    # workgroup, XCD remap), so they agree bitwise; no output depends on
-    # which workgroup computed it.
+        outs.setdefault((plan.get("kernel", 0), plan["reg_dims"], plan.get("loop_dims", 0)),
+                        []).append(out)
+    # Plans of one kernel with the same register dims (and looped-pencil
+    # mode, whose loop the compiler contracts into FMAs differently) evaluate
+    # each output with the same arithmetic whatever the schedule (LDS or
+    # global reads, slabs, cells per workgroup, XCD remap, streaming), so
+    # they agree bitwise; no output depends on which workgroup computed it.
     for group in outs.values():
         for o in group[1:]:
             assert np.array_equal(o, group[0])
@@ -184,7 +185,8 @@ def test_rk_steps_match_oracle_for_every_plan(precision, d, k, cells):
         S.rk_step(dt, case.steps)
         got = S.get_state()
         assert rel_l2(got, ref) <= tol, plan
-        outs.setdefault((plan.get("kernel", 0), plan["reg_dims"]), []).append(got)
+        outs.setdefault((plan.get("kernel", 0), plan["reg_dims"], plan.get("loop_dims", 0)),
+                        []).append(got)
     for group in outs.values():
         for o in group[1:]:
             assert np.array_equal(o, group[0])
