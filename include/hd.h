@@ -196,15 +196,33 @@ hd_status hd_stream_copy(const double *src, double *dst, size_t n, hd_stream str
 /* Message of the last error on this thread ("" if none). */
 const char *hd_last_error(void);
 
-/* Several bound solvers advanced together: each RK stage of every active
- * solve runs in one persistent launch over a shared work list, and a whole
- * step (5 launches) is replayed from one hipGraph. The solvers stay owned
- * by the caller and must outlive the batch. */
+/* Batched stepping of many independent solves (Sec. 5.4 time stepping of
+ * each; any d, degree, size, precision and plan in one batch).
+ * hd_batch_step advances every active solve by one LSRK step with ONE
+ * hipGraph replay: each solve's five fused stage launches - the same
+ * kernels and parameters as the solve stepped alone, so its result is
+ * bitwise the same - form a chain, and the chains run on up to eight
+ * independent graph branches. The graph is captured at the first step and
+ * again whenever the active set, a time step, a solution-buffer parity or a
+ * solver's plan, field or memory changed; two graphs are cached
+ * (alternating parities).
+ * Ownership: `solvers` (n pointers, read during the call) stay owned by the
+ * caller, must stay bound and outlive the batch; destroying or re-binding
+ * a member while the batch is used is undefined.
+ * Errors: HD_ERR_INVALID for NULL arguments, n outside 1..1024, an unbound
+ * solver or one listed twice; HD_ERR_OOM; HD_ERR_HIP if stream, event or
+ * graph set-up fails. */
 hd_status hd_batch_create(hd_solver *const *solvers, int n, hd_batch **out);
 hd_status hd_batch_destroy(hd_batch *b);
 
-/* One RK step of every solver i with active[i] != 0 (active may be NULL =
- * all), with time step dt[i]. */
+/* One RK step of every solver i with active[i] != 0 (active = NULL: all),
+ * with time step dt[i] (host arrays of n entries; dt is ignored for
+ * inactive solves). Enqueued on `stream`, asynchronous; nothing is launched
+ * if no solve is active. Each active solver's solution ends in its other
+ * buffer (hd_state_ptr follows). Calls that overlap on one solver race.
+ * Errors: HD_ERR_INVALID for NULL b or dt, a non-finite dt of an active
+ * solve, or a member that lost its workspace; HD_ERR_HIP for capture or
+ * launch failures. */
 hd_status hd_batch_step(hd_batch *b, const double *dt, const int *active, hd_stream stream);
 
 #ifdef __cplusplus

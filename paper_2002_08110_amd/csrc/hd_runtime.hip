@@ -1,7 +1,7 @@
 // C ABI of the library (declared in include/hd.h): solver objects, argument
 // checking, workspace layout, field tables, initial states, the fused RK
 // stage launches, hipGraph capture of whole RK steps, deterministic FP64
-// diagnostics and the batched persistent-launch path.
+// diagnostics (batched stepping is in hd_batch.hip).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

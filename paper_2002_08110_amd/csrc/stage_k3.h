@@ -64,8 +64,7 @@ constexpr int k3_waves_per_eu() {
 // of re-reading it.
 constexpr int kOptKeepU64 = 2;
 
-// One workgroup's cell `cell` (the kernel below and the batched persistent
-// kernel call it; lds_reuse as in stage_body).
+// One workgroup's cell `cell` (lds_reuse as in stage_body).
 template <typename P, int OPT>
 __device__ __forceinline__ void stage_k3_body(const StageParams<P> &prm, unsigned cell,
                                               unsigned char *smem_raw, bool lds_reuse) {

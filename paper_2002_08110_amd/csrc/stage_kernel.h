@@ -171,8 +171,8 @@ __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned t
     cell = (unsigned)(p / T);
     t0 = (unsigned)(p - (uint64_t)cell * T);
   }
-  // (A workgroup wider than cells_per_wg * T - the batched kernel's fixed
-  // 256 threads - leaves the extra threads inactive.)
+  // (Threads beyond cells_per_wg units of a workgroup, if any, stay
+  // inactive.)
   const bool active = cell < prm.ncells && (!USE_LDS || lc < prm.cells_per_wg);
   if constexpr (!USE_LDS) {
     if (!active) return;

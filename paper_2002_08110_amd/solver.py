@@ -186,9 +186,9 @@ class Solver:
 
 
 class Batch:
-    """hd_batch over bound Solvers (any d, degree, size, precision): per RK
-    stage one persistent launch per group of solves sharing a launch plan,
-    one hipGraph replay per step."""
+    """hd_batch over bound Solvers (any d, degree, size, precision, plan):
+    one hipGraph replay per step advances every active solve, each solve's
+    own stage launches on parallel graph branches."""
 
     def __init__(self, solvers):
         self.lib = _hd.load()
