@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="6d", choices=["6d", "4d", "6d_small", "2d"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the serving trace in the default run")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--precisions", default="fp64,fp32")
     ap.add_argument("--plan", default="", help="override plan, e.g. lds=1,reg_dims=1")
@@ -231,14 +233,14 @@ def run_batch(steps, seq_steps):
     print(json.dumps(res), flush=True)
 
 
-def run_serve(n_requests, steps_scale, load, fill):
+def run_serve(n_requests, steps_scale, load, fill, quiet=False):
     """The first n_requests requests of the seeded serving trace (Poisson
     arrivals at 20 req/s; d in {4,5,6}, k in {2..5}, 1e6-2e9 DoFs), each
     request's step count scaled by steps_scale, served with continuous
     batching in FP32 operator mode, and one at a time in FP64 on the same
     arrivals. A second batched run stretches the arrivals to the offered
-    load `load` (relative to the measured batched throughput). Prints one
-    JSON line."""
+    load `load` (relative to the measured batched throughput; 0: skip).
+    Returns the results; prints them as one JSON line unless quiet."""
     from paper_2002_08110_amd import serve
     from paper_2002_08110_amd import workloads as W
     trace = W.serve_trace()[:n_requests]
@@ -248,7 +250,8 @@ def run_serve(n_requests, steps_scale, load, fill):
     span = max(q.arrival for q in trace)
 
     def log(msg):
-        print("# " + msg, file=sys.stderr, flush=True)
+        if not quiet:
+            print("# " + msg, file=sys.stderr, flush=True)
 
     out = {"metric": "served DoF-updates/s and completion latency (request trace)",
            "requests": len(trace), "steps_scale": steps_scale, "work_dof_updates": work,
@@ -265,12 +268,15 @@ def run_serve(n_requests, steps_scale, load, fill):
         _, c = serve.serve(trace, precision="fp32", batched=True, time_scale=scale, log=log,
                            fill_dofs=fill)
         out["stretched"] = {"offered_load": load, "time_scale": scale, "batched_fp32": c}
-    print(json.dumps(out), flush=True)
+    if not quiet:
+        print(json.dumps(out), flush=True)
+    return out
 
 
-def profiled_traffic(precision, plan_override):
-    """Bytes per stage launch from the committed byte-counter profile of the
-    default plan, or None if the kernel source changed since it was taken."""
+def profiled_kernel(precision, plan_override):
+    """The committed counter profile of the default plan's stage kernel
+    (bytes per launch, VALU activity), or None if the kernel source changed
+    since it was taken."""
     if plan_override:
         return None
     from paper_2002_08110_amd import profiling
@@ -284,7 +290,7 @@ def profiled_traffic(precision, plan_override):
     want = "stage_k3_kernel<double" if precision == "fp64" else "stage_k3_kernel<float"
     for name, d in data["kernels"].items():
         if want in name:
-            return d["bytes_per_launch"]
+            return d
     return None
 
 
@@ -356,6 +362,7 @@ def main():
                  results[prec]["plan"]), file=sys.stderr, flush=True)
     head = results.get("fp64") or next(iter(results.values()))
     achieved = head["stage_kernel_GBps"]
+    prof = profiled_kernel(head["precision"], plan) if args.config == "6d" else None
     line = {
         "metric": "6D k=3 DoF-updates/s per RK stage, FP64 vs FP32, % HBM peak; p99 latency",
         "value": head["dof_updates_per_s"],
@@ -375,9 +382,11 @@ def main():
                    "rk": "LSRK45 (5 fused stages per step)", "cfl": case.cfl},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
-                     "traffic": profiled_traffic(head["precision"], plan)
-                     if args.config == "6d" else None,
-                     "kernel": "stage_kernel (fused LSRK stage)",
+                     "traffic": prof["bytes_per_launch"] if prof else None,
+                     "valu_busy_pct": prof.get("valu_busy_pct") if prof else None,
+                     "kernel": ("stage_k3_kernel (6D degree-3 fused LSRK stage)"
+                                if head["plan"].get("kernel") == 1
+                                else "stage_kernel (fused LSRK stage)"),
                      "algorithmic_bytes_per_dof": head["algorithmic_bytes_per_dof"]},
         "pct_hbm_peak": 100.0 * achieved / HBM_PEAK_GBPS,
         "modes": {p: {k: r[k] for k in ("dof_updates_per_s", "ms_per_step", "stage_ms",
@@ -388,6 +397,21 @@ def main():
                           "hardware": "1 SuperMUC-NG node, 2x24-core Xeon 8174, FP64, "
                                       "Gauss quadrature, deformed mesh"},
     }
+    if not args.no_serve and args.config == "6d":
+        # The metric's latency part: the serving trace (batched FP32 against
+        # one-at-a-time FP64), without the stretched-arrival run.
+        sv = run_serve(args.requests, args.steps_scale, 0.0, args.fill_dofs, quiet=True)
+        b, f = sv["batched_fp32"], sv["one_at_a_time_fp64"]
+        line["serving"] = {
+            "requests": sv["requests"], "offered_load": sv["offered_load"],
+            "latency_p99_s": b["latency_p99_s"], "latency_p50_s": b["latency_p50_s"],
+            "dof_updates_per_s": b["dof_updates_per_s"], "throughput_req_s": b["throughput_req_s"],
+            "precision": "fp32 operator, batched",
+            "one_at_a_time_fp64": {k: f[k] for k in ("latency_p99_s", "latency_p50_s",
+                                                     "dof_updates_per_s", "throughput_req_s")}}
+        print("# serving: p50 %.3f s, p99 %.3f s (one at a time FP64: %.3f / %.3f s)"
+              % (b["latency_p50_s"], b["latency_p99_s"], f["latency_p50_s"], f["latency_p99_s"]),
+              file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -66,6 +66,9 @@ def counters(run_dir, copy_mib, out_json, out_md):
     res = {"kernel_source_digest": kernel_source_digest(), "copy_mib": copy_mib,
            "copy_fetch_kib": cf, "copy_write_kib": cw,
            "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
+    valu = {}
+    if os.path.exists(csvp("valu")):
+        valu, _ = _counter_means(csvp("valu"))
     for (k, c), v in fetch.items():
         if "stage" not in k:
             continue
@@ -74,6 +77,10 @@ def counters(run_dir, copy_mib, out_json, out_md):
             "launches": nf[(k, c)], "fetch_kib": v, "write_kib": wv,
             "bytes_per_launch": (v * f_scale + wv * w_scale) * 1024.0,
         }
+        if (k, "VALUBusy") in valu:
+            res["kernels"][k]["valu_busy_pct"] = valu[(k, "VALUBusy")]
+            res["kernels"][k]["flops_fp64_per_launch"] = valu.get((k, "SQ_INSTS_VALU_FLOPS_FP64"))
+            res["kernels"][k]["flops_fp32_per_launch"] = valu.get((k, "SQ_INSTS_VALU_FLOPS_FP32"))
     with open(out_json, "w") as f:
         json.dump(res, f, indent=1)
     lines = ["# Byte counters of the fused stage kernels", "",
@@ -85,10 +92,21 @@ def counters(run_dir, copy_mib, out_json, out_md):
         lines.append("| `%s` | %d | %.4g | %.4g | %.4g GB |" % (k, d["launches"], d["fetch_kib"],
                                                                 d["write_kib"],
                                                                 d["bytes_per_launch"] / 1e9))
+    if any("valu_busy_pct" in d for d in res["kernels"].values()):
+        lines += ["", "VALU activity (derived counter VALUBusy = active VALU cycles / CUs / GPU",
+                  "busy cycles; VALU FLOP counters per launch):", "",
+                  "| kernel | VALUBusy % | FP64 FLOP/launch | FP32 FLOP/launch |", "|---|---|---|---|"]
+        for k, d in res["kernels"].items():
+            if "valu_busy_pct" in d:
+                lines.append("| `%s` | %.1f | %.4g | %.4g |" % (
+                    k, d["valu_busy_pct"], d["flops_fp64_per_launch"] or 0,
+                    d["flops_fp32_per_launch"] or 0))
     lines += ["", "Commands (one counter per run, from the repository root after",
               "`cd /tmp && export TMPDIR=/tmp`):", "", "```"]
     for name, cnt, mode in (("fetch", "FETCH_SIZE", "--mode stages --steps 2"),
                             ("write", "WRITE_SIZE", "--mode stages --steps 2"),
+                            ("valu", "VALUBusy SQ_INSTS_VALU_FLOPS_FP64 SQ_INSTS_VALU_FLOPS_FP32",
+                             "--mode stages --steps 2"),
                             ("cfetch", "FETCH_SIZE", "--mode copy --copy-mib %d" % copy_mib),
                             ("cwrite", "WRITE_SIZE", "--mode copy --copy-mib %d" % copy_mib)):
         lines.append("rocprofv3 --pmc %s --output-format csv -d gpurun_out/prof/%s -o %s -- "
