@@ -74,6 +74,10 @@ def _load():
         lib.or_field_sine_table.argtypes = [P(Mesh), ctypes.c_int, d, P(d)]
         lib.or_diagnostics.argtypes = [P(Mesh), ctypes.c_int, P(d), P(d), P(d)]
         lib.or_num_threads.argtypes = []
+        lib.or_vp_density.argtypes = [P(Mesh), ctypes.c_int, P(d), P(d)]
+        lib.or_vp_field.argtypes = [P(Mesh), ctypes.c_int, ctypes.c_int, P(d), P(d)]
+        lib.or_vp_rk_steps.argtypes = [P(Mesh), ctypes.c_int, ctypes.c_int, ctypes.c_int, d,
+                                       ctypes.c_int, P(d)]
         _lib = lib
     return _lib
 
@@ -193,6 +197,100 @@ class Problem:
                                     ctypes.byref(m), ctypes.byref(e))
         assert r == 0
         return m.value, e.value
+
+
+class VlasovPoisson:
+    """The Vlasov-Poisson system of Sec. 6 on a periodic x-box times a
+    periodic v-box (dim_x == dim_v): f_t + v.grad_x f - E.grad_v f = 0,
+    -Laplace phi = 1 - rho, E = -grad phi, rho = int f dv, with the field
+    solved spectrally from the modes |m_j| <= modes (see oracle.h)."""
+
+    def __init__(self, dim_x, dim_v, cells, lo, hi, k, modes):
+        if dim_x != dim_v:
+            raise ValueError("Vlasov-Poisson needs dim_x == dim_v")
+        self.lib = _load()
+        self.dim_x, self.dim_v, self.k, self.modes = dim_x, dim_v, k, int(modes)
+        self.d = dim_x + dim_v
+        self.n = k + 1
+        self.cells = [int(c) for c in cells]
+        self.lo = [float(x) for x in lo]
+        self.hi = [float(x) for x in hi]
+        self.mesh = make_mesh(dim_x, dim_v, cells, lo, hi)
+        self.ndofs = int(self.lib.or_num_dofs(ctypes.byref(self.mesh), k))
+        self.npoints = int(np.prod(self.cells[:dim_x])) * self.n ** dim_x
+
+    def density(self, u):
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        rho = np.empty(self.npoints)
+        assert self.lib.or_vp_density(ctypes.byref(self.mesh), self.k, _dp(u), _dp(rho)) == 0
+        return rho
+
+    def field(self, rho):
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        E = np.empty(self.npoints * self.dim_x)
+        assert self.lib.or_vp_field(ctypes.byref(self.mesh), self.k, self.modes, _dp(rho),
+                                    _dp(E)) == 0
+        return E
+
+    def advection(self, u):
+        """The advection problem a = (v, -E) with the field of state u."""
+        return Problem(self.dim_x, self.dim_v, self.cells, self.lo, self.hi, self.k,
+                       field="phase", E=self.field(self.density(u)), sign=-1.0)
+
+    def apply(self, u, mode=1):
+        return self.advection(u).apply(u, mode)
+
+    def rk_steps(self, u, dt, nsteps, mode=1):
+        u = np.array(u, dtype=np.float64, copy=True)
+        r = self.lib.or_vp_rk_steps(ctypes.byref(self.mesh), self.k, self.modes, mode, dt,
+                                    nsteps, _dp(u))
+        if r:
+            raise RuntimeError("or_vp_rk_steps failed")
+        return u
+
+    def stable_dt(self, u, cfl=0.2):
+        return self.advection(u).stable_dt(cfl)
+
+    def x_weights(self):
+        """GL quadrature weight of each x-point (E table order)."""
+        xi, w = gl_rule(self.k)
+        W = np.ones(self.npoints)
+        p = np.arange(self.npoints)
+        nxn = self.n ** self.dim_x
+        xc, xn = p // nxn, p % nxn
+        for j in range(self.dim_x):
+            h = (self.hi[j] - self.lo[j]) / self.cells[j]
+            W = W * h * w[xn % self.n]
+            xc //= self.cells[j]
+            xn //= self.n
+        return W
+
+    def x_coords(self):
+        """Coordinates of the x-points, shape (npoints, dim_x)."""
+        xi, w = gl_rule(self.k)
+        p = np.arange(self.npoints)
+        nxn = self.n ** self.dim_x
+        xc, xn = p // nxn, p % nxn
+        X = np.empty((self.npoints, self.dim_x))
+        for j in range(self.dim_x):
+            h = (self.hi[j] - self.lo[j]) / self.cells[j]
+            X[:, j] = self.lo[j] + (xc % self.cells[j] + xi[xn % self.n]) * h
+            xc //= self.cells[j]
+            xn //= self.n
+        return X
+
+    def electric_energy(self, E):
+        """1/2 int |E|^2 dx by GL quadrature over the x-points."""
+        E = np.asarray(E).reshape(self.npoints, self.dim_x)
+        return 0.5 * float(np.sum(self.x_weights()[:, None] * E * E))
+
+    def init_state(self, kind, params=None):
+        return Problem(self.dim_x, self.dim_v, self.cells, self.lo, self.hi, self.k,
+                       field="phase").init_state(kind, params)
+
+    def diagnostics(self, u):
+        return Problem(self.dim_x, self.dim_v, self.cells, self.lo, self.hi, self.k,
+                       field="phase").diagnostics(u)
 
 
 def gl_rule(k):

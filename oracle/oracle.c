@@ -604,6 +604,157 @@ int or_diagnostics(const or_mesh *mesh, int k, const double *u, double *mass,
   return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Vlasov-Poisson field (Sec. 6)                                            */
+/* ------------------------------------------------------------------------ */
+
+/* The x-points are the x-nodes of the x-cells: p = xcell * n^dx + xnode, both
+ * lexicographic with dim 1 fastest - the layout of the E table. */
+static void x_layout(const or_geom *g, int64_t *nxc, int64_t *nxn, int64_t *nvc,
+                     int64_t *nvn) {
+  *nxc = *nxn = *nvc = *nvn = 1;
+  for (int j = 0; j < g->dx; ++j) {
+    *nxc *= g->cells[j];
+    *nxn *= g->n;
+  }
+  for (int j = g->dx; j < g->d; ++j) {
+    *nvc *= g->cells[j];
+    *nvn *= g->n;
+  }
+}
+
+/* Coordinates and quadrature weight prod_j h_j w_{i_j} of x-point p. */
+static double x_point(const or_geom *g, int64_t p, int64_t nxn, double *x) {
+  int64_t xc = p / nxn, xn = p % nxn;
+  double W = 1.0;
+  for (int j = 0; j < g->dx; ++j) {
+    const int c = (int)(xc % g->cells[j]), i = (int)(xn % g->n);
+    xc /= g->cells[j];
+    xn /= g->n;
+    x[j] = g->lo[j] + (c + g->xi[i]) * g->h[j];
+    W *= g->h[j] * g->w[i];
+  }
+  return W;
+}
+
+int or_vp_density(const or_mesh *mesh, int k, const double *u, double *rho) {
+  or_geom g;
+  if (setup_geom(mesh, k, &g) || g.dx != g.dv) return -1;
+  int64_t nxc, nxn, nvc, nvn;
+  x_layout(&g, &nxc, &nxn, &nvc, &nvn);
+  const int64_t X = nxc * nxn;
+#pragma omp parallel for schedule(static)
+  for (int64_t p = 0; p < X; ++p) {
+    const int64_t xc = p / nxn, xn = p % nxn;
+    double s = 0.0;
+    for (int64_t cv = 0; cv < nvc; ++cv)
+      for (int64_t vn = 0; vn < nvn; ++vn) {
+        /* velocity quadrature weight prod_j h_{v_j} w_{i_{v_j}} */
+        double Wv = 1.0;
+        int64_t r = vn;
+        for (int j = g.dx; j < g.d; ++j) {
+          Wv *= g.h[j] * g.w[r % g.n];
+          r /= g.n;
+        }
+        const int64_t cell = xc + nxc * cv, node = xn + nxn * vn;
+        s += Wv * u[cell * g.nd + node];
+      }
+    rho[p] = s;
+  }
+  return 0;
+}
+
+int or_vp_field(const or_mesh *mesh, int k, int M, const double *rho, double *E) {
+  or_geom g;
+  if (setup_geom(mesh, k, &g) || g.dx != g.dv || M < 1) return -1;
+  int64_t nxc, nxn, nvc, nvn;
+  x_layout(&g, &nxc, &nxn, &nvc, &nvn);
+  const int64_t X = nxc * nxn;
+  double vol = 1.0;
+  for (int j = 0; j < g.dx; ++j) vol *= g.hi[j] - g.lo[j];
+  for (int64_t i = 0; i < X * g.dx; ++i) E[i] = 0.0;
+  int64_t nmodes = 1;
+  for (int j = 0; j < g.dx; ++j) nmodes *= 2 * M + 1;
+  for (int64_t mi = 0; mi < nmodes; ++mi) {
+    /* wave vector k_j = 2 pi m_j / L_j, m_j in -M..M */
+    double kv[3] = {0, 0, 0}, k2 = 0.0;
+    int64_t r = mi;
+    int zero = 1;
+    for (int j = 0; j < g.dx; ++j) {
+      const int m = (int)(r % (2 * M + 1)) - M;
+      r /= 2 * M + 1;
+      if (m) zero = 0;
+      kv[j] = 2.0 * OR_PI * m / (g.hi[j] - g.lo[j]);
+      k2 += kv[j] * kv[j];
+    }
+    if (zero) continue; /* the mean is balanced by the background */
+    /* rho_hat = (1/|Omega_x|) int rho exp(-i k.x) dx, GL quadrature in x */
+    double re = 0.0, im = 0.0;
+    for (int64_t p = 0; p < X; ++p) {
+      double x[3];
+      const double W = x_point(&g, p, nxn, x);
+      double ph = 0.0;
+      for (int j = 0; j < g.dx; ++j) ph += kv[j] * x[j];
+      re += W * rho[p] * cos(ph);
+      im -= W * rho[p] * sin(ph);
+    }
+    re /= vol;
+    im /= vol;
+    /* -Laplace phi = 1 - rho, E = -grad phi: E_hat_j = i k_j rho_hat / |k|^2 */
+    for (int64_t p = 0; p < X; ++p) {
+      double x[3];
+      x_point(&g, p, nxn, x);
+      double ph = 0.0;
+      for (int j = 0; j < g.dx; ++j) ph += kv[j] * x[j];
+      const double c = cos(ph), s = sin(ph);
+      for (int j = 0; j < g.dx; ++j) {
+        const double cre = -kv[j] / k2 * im, cim = kv[j] / k2 * re;
+        E[p * g.dx + j] += cre * c - cim * s; /* Re[(cre + i cim) exp(i ph)] */
+      }
+    }
+  }
+  return 0;
+}
+
+int or_vp_rk_steps(const or_mesh *mesh, int k, int M, int mode, double dt, int nsteps,
+                   double *u) {
+  or_geom g;
+  if (setup_geom(mesh, k, &g) || g.dx != g.dv) return -1;
+  int64_t nxc, nxn, nvc, nvn;
+  x_layout(&g, &nxc, &nxn, &nvc, &nvn);
+  const int64_t X = nxc * nxn, N = g.nd * g.ncells;
+  double A[5], B[5], C[5];
+  or_lsrk45_coefficients(A, B, C);
+  double *du = (double *)calloc((size_t)N, sizeof(double));
+  double *L = (double *)malloc(sizeof(double) * (size_t)N);
+  double *rho = (double *)malloc(sizeof(double) * (size_t)X);
+  double *E = (double *)malloc(sizeof(double) * (size_t)(X * g.dx));
+  int r = (!du || !L || !rho || !E) ? -1 : 0;
+  or_field f;
+  memset(&f, 0, sizeof(f));
+  f.kind = 1;
+  f.E = E;
+  f.sign = -1.0; /* electrons: a = (v, -E) */
+  for (int step = 0; step < nsteps && !r; ++step)
+    for (int st = 0; st < 5 && !r; ++st) {
+      /* the field of the stage's own input */
+      r = or_vp_density(mesh, k, u, rho);
+      if (!r) r = or_vp_field(mesh, k, M, rho, E);
+      if (!r) r = or_apply(mesh, k, &f, mode, u, L);
+      if (r) break;
+#pragma omp parallel for schedule(static)
+      for (int64_t i = 0; i < N; ++i) {
+        du[i] = A[st] * du[i] + dt * L[i];
+        u[i] = u[i] + B[st] * du[i];
+      }
+    }
+  free(du);
+  free(L);
+  free(rho);
+  free(E);
+  return r;
+}
+
 int or_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

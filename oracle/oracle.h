@@ -110,6 +110,23 @@ int or_field_sine_table(const or_mesh *mesh, int k, double amp, double *E);
 int or_diagnostics(const or_mesh *mesh, int k, const double *u, double *mass,
                    double *energy);
 
+/* Vlasov-Poisson field (Sec. 6; electrons on a neutralizing background,
+ * dim_x == dim_v), with x-points p = xcell * n^dx + xnode as in the E table:
+ *  or_vp_density: rho(x_p) = int f(x_p, v) dv, Gauss-Lobatto quadrature in v
+ *                 (exact for the DG polynomial).
+ *  or_vp_field:   -Laplace phi = 1 - rho, E = -grad phi on the periodic x-box,
+ *                 solved spectrally with the modes m in [-M, M]^dx, m != 0:
+ *                 rho_hat_m = |Omega_x|^-1 sum_p W_p rho_p exp(-i k_m.x_p)
+ *                 (GL quadrature in x), k_m = 2 pi m / L, and
+ *                 E(x_p) = sum_m Re[i k_m rho_hat_m / |k_m|^2 exp(i k_m.x_p)];
+ *                 E[p * dx + j] as the or_field table.
+ *  or_vp_rk_steps: LSRK steps of f_t + v.grad_x f - E.grad_v f = 0 with the
+ *                 field recomputed from each stage's input (a = (v, -E)). */
+int or_vp_density(const or_mesh *mesh, int k, const double *u, double *rho);
+int or_vp_field(const or_mesh *mesh, int k, int M, const double *rho, double *E);
+int or_vp_rk_steps(const or_mesh *mesh, int k, int M, int mode, double dt, int nsteps,
+                   double *u);
+
 /* Number of OpenMP threads the oracle uses. */
 int or_num_threads(void);
 
