@@ -43,11 +43,13 @@ def parse():
     ap.add_argument("--precisions", default="fp64,fp32")
     ap.add_argument("--plan", default="", help="override plan, e.g. lds=1,reg_dims=1")
     ap.add_argument("--mode", default="bench",
-                    choices=["bench", "stages", "copy", "batch", "serve"],
+                    choices=["bench", "stages", "copy", "batch", "serve", "vp"],
                     help="stages: only run --steps x 5 stage launches per precision (for "
                          "profilers); copy: a plain device copy of --copy-mib MiB (the "
                          "calibration kernel for the byte counters); batch: the 96-solve "
-                         "mix; serve: a prefix of the seeded request trace")
+                         "mix; serve: a prefix of the seeded request trace; vp: the 6D "
+                         "Vlasov-Poisson stage (self-consistent field each stage)")
+    ap.add_argument("--modes", type=int, default=4, help="vp: Fourier modes per x-dimension")
     ap.add_argument("--copy-mib", type=int, default=4096)
     ap.add_argument("--requests", type=int, default=24, help="serve: trace prefix length")
     ap.add_argument("--steps-scale", type=float, default=1.0,
@@ -273,6 +275,79 @@ def run_serve(n_requests, steps_scale, load, fill, quiet=False):
     return out
 
 
+# One Vlasov-Poisson RK stage of the 6D 8^6-cell k=3 run on one 48-core
+# SuperMUC-NG node, read off the weak-scaling figure (Fig. vp:scalingprofile).
+PAPER_VP_STAGE_S = 0.955
+
+
+def run_vp(steps, warmup, precisions, modes):
+    """6D Vlasov-Poisson (Sec. 6): Landau-damping initial state on 8^6
+    cells, degree 3, x in [0, 4 pi]^3, v in [-6, 6]^3, the field solved from
+    the density at every stage. Times the graph-captured RK step, the field
+    pre-pass alone (density, transforms, E table) and the stage with the
+    field frozen (the advection kernel alone). Prints one JSON line."""
+    import torch
+
+    from paper_2002_08110_amd import workloads as W
+    from paper_2002_08110_amd.solver import Solver
+    case = W.landau_case("6d_vlasov_poisson_8^6_k3", 3, [8] * 6, 3, steps, modes=modes)
+    stream = torch.cuda.current_stream()
+
+    def ev_ms(fn, reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {"metric": "6D Vlasov-Poisson DoF-updates/s per RK stage (field solved each stage)",
+           "unit": "DoF-updates/s", "workload": case.name, "ndofs": case.ndofs, "modes": modes,
+           "paper_context": {"stage_s": PAPER_VP_STAGE_S,
+                             "hardware": "1 SuperMUC-NG node (48 cores), FP64, multigrid "
+                                         "Poisson"},
+           "modes_result": {}}
+    for prec in precisions:
+        S = Solver(3, 3, case.cells, case.lo, case.hi, 3, precision=prec)
+        S.apply_tuned_plan()
+        S.set_field_vlasov_poisson(modes)
+        S.init_state(case.ic, list(case.ic_params))
+        torch.cuda.synchronize()
+        dt = S.stable_dt(case.cfl)
+        m0, _ = S.diagnostics()
+        S.rk_step(dt, warmup)
+        step_ms = ev_ms(lambda: S.rk_step(dt, steps), 1) / steps
+        field_ms = ev_ms(lambda: S.compute_field(), 10)
+        # the same stage kernels with the field frozen at the current state
+        E = S.get_field()
+        m1, _ = S.diagnostics()
+        S.set_field_phase_space(E, -1.0)
+        S.rk_step(dt, 1)
+        adv_ms = ev_ms(lambda: S.rk_step(dt, steps), 1) / steps / 5
+        S.close()
+        del S
+        torch.cuda.empty_cache()
+        stage_ms = step_ms / 5
+        gbps = 8.0 * case.ndofs / (field_ms * 1e-3) / 1e9
+        out["modes_result"][prec] = {
+            "dof_updates_per_s": case.ndofs / (stage_ms * 1e-3), "stage_ms": stage_ms,
+            "field_ms": field_ms, "advection_stage_ms": adv_ms,
+            "field_fraction": field_ms / stage_ms, "dt": dt, "mass_drift": (m1 - m0) / abs(m0),
+            "field_pass_GBps": gbps, "speedup_vs_paper_node": PAPER_VP_STAGE_S / (stage_ms * 1e-3)}
+        print("# vp %s: stage %.3f ms (field %.3f ms at %.0f GB/s of f, advection %.3f ms)"
+              % (prec, stage_ms, field_ms, gbps, adv_ms), file=sys.stderr, flush=True)
+    head = out["modes_result"].get("fp64") or next(iter(out["modes_result"].values()))
+    out["value"] = head["dof_updates_per_s"]
+    out["roofline"] = {"bound": "hbm", "kernel": "Vlasov-Poisson field pre-pass (reads f once)",
+                       "achieved": head["field_pass_GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                       "frac": head["field_pass_GBps"] / HBM_PEAK_GBPS,
+                       "algorithmic_bytes_per_dof": 8.0}
+    print(json.dumps(out), flush=True)
+
+
 def profiled_kernel(precision, plan_override):
     """The committed counter profile of the default plan's stage kernel
     (bytes per launch, VALU activity), or None if the kernel source changed
@@ -348,6 +423,9 @@ def main():
         return
     if args.mode == "serve":
         run_serve(args.requests, args.steps_scale, args.load, args.fill_dofs)
+        return
+    if args.mode == "vp":
+        run_vp(args.steps, args.warmup, args.precisions.split(","), args.modes)
         return
     if args.mode == "stages":
         for prec in args.precisions.split(","):

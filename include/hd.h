@@ -148,6 +148,36 @@ hd_status hd_set_field_phase_space(hd_solver *s, const double *E_host, double si
  * at the configuration nodes. Requires hd_bind. Synchronous. */
 hd_status hd_set_field_sine(hd_solver *s, double amp, double sign);
 
+/* Vlasov-Poisson field (Sec. 6, eq. vp:close): electrons on a neutralizing
+ * background, a = (v, -E) with E recomputed from the input of every RK
+ * stage (and of hd_apply) on the device, before the stage kernel, in the
+ * same stream (and the same captured graph):
+ *   rho(x) = int f dv            (GL quadrature over the velocity cells),
+ *   -Laplace phi = 1 - rho,  E = -grad phi   on the periodic x-box,
+ * solved spectrally: the Fourier coefficients of rho for the modes
+ * |m_j| <= modes (exact discrete transforms over the GL nodes with the GL
+ * weights), E_hat = i k rho_hat / |k|^2 (mode 0 dropped: the background
+ * balances the mean), E = sum_m Re(E_hat e^{i k.x}) at the x-nodes.
+ * The field is computed in FP64; FP32 solvers round it to FP32 for the
+ * stage kernels. On C uniform cells the nodal pattern that repeats in every
+ * cell transforms onto the modes that are multiples of C: for a physical
+ * field keep modes below every x-dimension's cell count.
+ * Requires dim_x == dim_v, 1 <= modes <= 16 and hd_bind.
+ * Synchronous (uploads the transform matrices). */
+hd_status hd_set_field_vlasov_poisson(hd_solver *s, int modes);
+
+/* Copy the field table E to E_host (nE = (#x-cells)(k+1)^dx * dx doubles,
+ * laid out as in hd_set_field_phase_space). For the Vlasov-Poisson field it
+ * is first recomputed from the current state on `stream`; for a constant
+ * field the table holds a_v at every x-node. Waits for `stream`. Requires
+ * hd_bind and dim_x == dim_v. */
+hd_status hd_get_field(hd_solver *s, double *E_host, hd_stream stream);
+
+/* For the Vlasov-Poisson field: recompute the device E table from the
+ * current state on `stream` (Sec. 6, steps 1-4 of a stage; asynchronous).
+ * A no-op for prescribed fields. Requires hd_bind. */
+hd_status hd_compute_field(hd_solver *s, hd_stream stream);
+
 /* Copy a canonical FP64 state (host or device pointer) into the solution. */
 hd_status hd_set_state(hd_solver *s, const double *u, int u_is_device, hd_stream stream);
 
@@ -170,7 +200,9 @@ hd_status hd_get_state(const hd_solver *s, double *u_host, hd_stream stream);
  * out: N values on the device, FP64 for HD_FP64 and FP32 for HD_FP32. */
 hd_status hd_apply(hd_solver *s, const double *in_dev, void *out_dev, hd_stream stream);
 
-/* dt = cfl / ((2k+1) sum_j max|a_j| / h_j) for the current field. */
+/* dt = cfl / ((2k+1) sum_j max|a_j| / h_j) for the current field. For the
+ * Vlasov-Poisson field, E is that of the current state, computed on the
+ * null stream (which waits for blocking streams) before this returns. */
 hd_status hd_stable_dt(const hd_solver *s, double cfl, double *dt);
 
 /* One stage (stage = 0..4) of the low-storage RK scheme (Sec. 5.4), fused

@@ -36,11 +36,21 @@ struct hd_solver {
   double gdt = 0.0;
   bool gvalid = false;
   uint64_t version = 0;  // bumped when the plan, field or memory changes
+  // Vlasov-Poisson field (field_kind 2): modes per dimension and scratch.
+  int vp_modes = 0, vp_groups = 0;
+  size_t off_vp_partial = 0, off_vp_wv = 0, off_vp_A = 0, off_vp_B = 0, off_vp_Eh = 0,
+         off_vp_mats = 0;
 
   double *u(int i) const { return reinterpret_cast<double *>(ws + off_u[i]); }
   void *du() const { return ws + off_du; }
   void *E() const { return ws + off_E; }
   double *part() const { return reinterpret_cast<double *>(ws + off_part); }
+  double *vp_partial() const { return reinterpret_cast<double *>(ws + off_vp_partial); }
+  double *vp_wv() const { return reinterpret_cast<double *>(ws + off_vp_wv); }
+  double2 *vp_bufA() const { return reinterpret_cast<double2 *>(ws + off_vp_A); }
+  double2 *vp_bufB() const { return reinterpret_cast<double2 *>(ws + off_vp_B); }
+  double2 *vp_Ehat() const { return reinterpret_cast<double2 *>(ws + off_vp_Eh); }
+  double2 *vp_mats() const { return reinterpret_cast<double2 *>(ws + off_vp_mats); }
   size_t psize() const { return prec == HD_FP32 ? sizeof(float) : sizeof(double); }
 };
 
@@ -78,6 +88,14 @@ const void *stage_entry(const hd_solver *s);
 // not changed.
 hd_status enqueue_step(hd_solver *s, int par, double dt, hipStream_t st);
 
+// Vlasov-Poisson field (hd_vp.hip): modes per dimension at most
+// kVpMaxModes; workspace layout from `off` (returns the end offset); upload
+// of the field matrices; enqueue of the field of state u into the E table.
+constexpr int kVpMaxModes = 16;
+size_t vp_layout(hd_solver *s, size_t off);
+hd_status vp_upload(hd_solver *s);
+hd_status vp_enqueue(hd_solver *s, const double *u, hipStream_t st);
+
 // Kernel parameters of a solver (everything but the per-launch fields:
 // buffers, mode, RK coefficients, dt). kernel = 1 passes constant fields in
 // the phase-space form the specialised kernel reads.
@@ -99,7 +117,9 @@ void fill_params(const hd_solver *s, StageParams<P> *prm, int kernel) {
   }
   for (int m = 0; m < s->n; ++m) prm->xi[m] = (P)s->tab.xi[m];
   for (int q = 0; q < s->n * s->n; ++q) prm->Dm[q] = (P)s->tab.D[q];
-  prm->field_kind = s->field_kind;
+  // The Vlasov-Poisson field (kind 2) is a phase-space field whose E table
+  // is recomputed before each stage.
+  prm->field_kind = s->field_kind == 0 ? 0 : 1;
   prm->esign = (P)s->esign;
   prm->E = reinterpret_cast<const P *>(s->E());
   prm->xcd_remap = s->plan.xcd_remap;

@@ -275,6 +275,11 @@ hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, in
                                     "nodes per thread");
   const void *fn = hd::rt::stage_entry(s);
   if (!fn) return fail(HD_ERR_HIP, "no compiled stage kernel for this plan");
+  if (s->field_kind == 2) {
+    // the Vlasov-Poisson field of this stage's input, into the E table
+    const hd_status vr = hd::rt::vp_enqueue(s, in, st);
+    if (vr != HD_OK) return vr;
+  }
   if (ls.shmem > 65536) {
     hipError_t ae = allow_large_lds(fn);
     if (ae != hipSuccess)
@@ -437,6 +442,12 @@ GeomArgs geom_of(const hd_solver *s) {
 // the constant a_v at every x-node (read by the specialised kernel).
 hd_status upload_E(hd_solver *s) {
   const size_t n = (size_t)s->nE;
+  if (s->field_kind == 2) {
+    // the table follows the state; only the transform matrices are uploaded
+    const hd_status r = hd::rt::vp_upload(s);
+    changed(s);
+    return r;
+  }
   if (s->field_kind == 0) {
     s->E_host.assign(n, 0.0);
     for (size_t i = 0; i < n; ++i) s->E_host[i] = s->a_const[s->dx + (int)(i % (size_t)s->dx)];
@@ -543,6 +554,7 @@ hd_status hd_create(const hd_mesh *mesh, int degree, int prec, hd_solver **out) 
   off = align_up(off + (size_t)s->nE * s->psize());
   s->off_part = off;
   off = align_up(off + sizeof(double) * (2 * kDiagBlocks + 2));
+  off = hd::rt::vp_layout(s, off);
   s->total = off;
   s->plan = default_plan(s);
   *out = s;
@@ -631,6 +643,49 @@ hd_status hd_set_field_sine(hd_solver *s, double amp, double sign) {
   return hd_set_field_phase_space(s, E.data(), sign);
 }
 
+hd_status hd_set_field_vlasov_poisson(hd_solver *s, int modes) {
+  if (!s) return fail(HD_ERR_INVALID, "NULL argument");
+  if (s->dx != s->dv) return fail(HD_ERR_INVALID, "Vlasov-Poisson field needs dim_x == dim_v");
+  hd_status r = check_bound(s);
+  if (r) return r;
+  if (modes < 1 || modes > hd::rt::kVpMaxModes)
+    return fail(HD_ERR_INVALID, "modes must be 1.." + std::to_string(hd::rt::kVpMaxModes));
+  s->field_kind = 2;
+  s->esign = -1.0;
+  s->vp_modes = modes;
+  return upload_E(s);
+}
+
+hd_status hd_compute_field(hd_solver *s, hd_stream stream) {
+  hd_status r = check_bound(s);
+  if (r) return r;
+  if (s->field_kind != 2) return HD_OK;
+  return hd::rt::vp_enqueue(s, s->u(s->cur), (hipStream_t)stream);
+}
+
+hd_status hd_get_field(hd_solver *s, double *E_host, hd_stream stream) {
+  hd_status r = check_bound(s);
+  if (r) return r;
+  if (!E_host) return fail(HD_ERR_INVALID, "NULL argument");
+  if (s->dx != s->dv) return fail(HD_ERR_INVALID, "the field table needs dim_x == dim_v");
+  const hipStream_t st = (hipStream_t)stream;
+  if (s->field_kind == 2) {
+    r = hd::rt::vp_enqueue(s, s->u(s->cur), st);
+    if (r) return r;
+  }
+  const size_t n = (size_t)s->nE;
+  if (s->prec == HD_FP32) {
+    std::vector<float> tmp(n);
+    HD_HIP(hipMemcpyAsync(tmp.data(), s->E(), n * sizeof(float), hipMemcpyDeviceToHost, st));
+    HD_HIP(hipStreamSynchronize(st));
+    for (size_t i = 0; i < n; ++i) E_host[i] = tmp[i];
+  } else {
+    HD_HIP(hipMemcpyAsync(E_host, s->E(), n * sizeof(double), hipMemcpyDeviceToHost, st));
+    HD_HIP(hipStreamSynchronize(st));
+  }
+  return HD_OK;
+}
+
 hd_status hd_set_state(hd_solver *s, const double *u, int u_is_device, hd_stream stream) {
   hd_status r = check_bound(s);
   if (r) return r;
@@ -687,6 +742,15 @@ hd_status hd_apply(hd_solver *s, const double *in, void *out, hd_stream stream) 
 hd_status hd_stable_dt(const hd_solver *s, double cfl, double *dt) {
   if (!s || !dt) return fail(HD_ERR_INVALID, "NULL argument");
   if (!(cfl > 0)) return fail(HD_ERR_INVALID, "cfl must be > 0");
+  // The Vlasov-Poisson field of the current state, computed on the null
+  // stream (ordered after the work of blocking streams).
+  std::vector<double> Evp;
+  if (s->field_kind == 2) {
+    Evp.resize((size_t)s->nE);
+    hd_status r = hd_get_field(const_cast<hd_solver *>(s), Evp.data(), nullptr);
+    if (r) return r;
+  }
+  const std::vector<double> &Et = s->field_kind == 2 ? Evp : s->E_host;
   double sum = 0.0;
   for (int j = 0; j < s->d; ++j) {
     double amax = 0.0;
@@ -699,7 +763,7 @@ hd_status hd_stable_dt(const hd_solver *s, double cfl, double *dt) {
           amax = std::max(amax, std::fabs(s->mesh.lo[m] + (c + s->tab.xi[q]) * s->h[m]));
     } else {
       for (int64_t t = j - s->dx; t < s->nE; t += s->dx)
-        amax = std::max(amax, std::fabs(s->esign * s->E_host[(size_t)t]));
+        amax = std::max(amax, std::fabs(s->esign * Et[(size_t)t]));
     }
     sum += amax / s->h[j];
   }

@@ -65,6 +65,8 @@ def make_solver(case, precision, tuned=True, bind=True):
 def setup(s, case):
     if case.field == "sine":
         s.set_field_sine(case.amp)
+    elif case.field == "vlasov_poisson":
+        s.set_field_vlasov_poisson(case.modes)
     else:
         s.set_field_constant(case.a)
     s.init_state(case.ic, list(case.ic_params))

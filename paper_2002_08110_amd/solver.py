@@ -93,6 +93,31 @@ class Solver:
         check(self.lib.hd_set_field_phase_space(
             self.h, E.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(sign)))
 
+    def set_field_vlasov_poisson(self, modes=4):
+        """a = (v, -E) with E solved from the density of every stage's input
+        (modes per x-dimension, at most 16)."""
+        check(self.lib.hd_set_field_vlasov_poisson(self.h, int(modes)))
+
+    @property
+    def field_entries(self):
+        n = self.dim_x
+        for j in range(self.dim_x):
+            n *= self.cells[j] * (self.k + 1)
+        return n
+
+    def get_field(self, stream=None) -> np.ndarray:
+        """The E table (x-points x dim_x, FP64); for the Vlasov-Poisson field
+        that of the current state."""
+        out = np.empty(self.field_entries, dtype=np.float64)
+        check(self.lib.hd_get_field(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    _stream(stream)))
+        return out
+
+    def compute_field(self, stream=None):
+        """Recompute the device E table of the Vlasov-Poisson field from the
+        current state (asynchronous; no-op for prescribed fields)."""
+        check(self.lib.hd_compute_field(self.h, _stream(stream)))
+
     # -- state ------------------------------------------------------------
     def set_state(self, u, stream=None):
         if isinstance(u, torch.Tensor):

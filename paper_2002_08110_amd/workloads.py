@@ -27,13 +27,15 @@ class Case:
     lo: list
     hi: list
     degree: int
-    field: str          # "constant" or "sine" (a = (v, amp sin(2 pi x)))
+    field: str          # "constant", "sine" (a = (v, amp sin(2 pi x))),
+                        # "table" (a given E) or "vlasov_poisson" (a = (v, -E[f]))
     a: list | None = None
     amp: float = 0.1
     ic: int = 0         # 0: prod sin(2 pi x); 1: perturbed Maxwellian
     ic_params: tuple = (0.0,)
     steps: int = 1
     cfl: float = 0.2
+    modes: int = 4      # Fourier modes per x-dimension of the Poisson solve
 
     @property
     def d(self):
@@ -48,6 +50,15 @@ def phase_space_case(name, dx, dv, cells, degree, steps, vmax=6.0, amp=0.1):
     return Case(name, dx, dv, list(cells), [0.0] * dx + [-vmax] * dv,
                 [1.0] * dx + [vmax] * dv, degree, "sine", amp=amp, ic=1,
                 ic_params=(0.01,), steps=steps)
+
+
+def landau_case(name, dx, cells, degree, steps, modes=4, alpha=0.01, kx=0.5, vmax=6.0):
+    """Linear Landau damping (Sec. 6): f0 = (1 + alpha cos(kx x_1)) times the
+    unit Maxwellian, x in [0, 2 pi / kx]^dx, v in [-vmax, vmax]^dx, with the
+    self-consistent Vlasov-Poisson field."""
+    L = 2.0 * math.pi / kx
+    return Case(name, dx, dx, list(cells), [0.0] * dx + [-vmax] * dx, [L] * dx + [vmax] * dx,
+                degree, "vlasov_poisson", ic=1, ic_params=(alpha,), steps=steps, modes=modes)
 
 
 # Configuration 1: 2D constant advection, exact solution u0(x - a t).

@@ -37,6 +37,9 @@ def oracle_problem(case: W.Case, E=None, sign=1.0):
     if case.field == "table":
         return oracle.Problem(case.dim_x, case.dim_v, case.cells, case.lo, case.hi, case.degree,
                               field="phase", E=E, sign=sign)
+    if case.field == "vlasov_poisson":
+        return oracle.VlasovPoisson(case.dim_x, case.dim_v, case.cells, case.lo, case.hi,
+                                    case.degree, case.modes)
     raise ValueError(case.field)
 
 
@@ -50,6 +53,8 @@ def gpu_solver(case: W.Case, precision="fp64", E=None, sign=1.0, plan=None):
         s.set_field_sine(case.amp, sign)
     elif case.field == "table":
         s.set_field_phase_space(E, sign)
+    elif case.field == "vlasov_poisson":
+        s.set_field_vlasov_poisson(case.modes)
     if plan:
         s.set_plan(**plan)
     return s

@@ -70,6 +70,20 @@ def test_field_of_a_uniform_density_vanishes_and_modes_truncate():
     assert np.abs(vp.field(1 + np.cos(2 * np.pi * 3 * x))).max() < 1e-12
 
 
+@pytest.mark.parametrize("C", [2, 3, 5])
+def test_constant_density_aliases_only_onto_multiples_of_the_cell_count(C):
+    # On C uniform cells, sum_c exp(-2 pi i m c / C) vanishes unless C | m:
+    # a constant density (every cell alike) has rho_hat_m = 0 for the other
+    # m != 0, and a nonzero field exactly when some |m| <= M is a multiple of C.
+    for M in (1, 2, 3, 4):
+        vp = oracle.VlasovPoisson(1, 1, [C, 2], [0.5, -1], [2.5, 1], 3, M)
+        E = vp.field(np.full(C * 4, 2.0))
+        if M >= C:
+            assert np.abs(E).max() > 1e-3, (C, M)
+        else:
+            assert np.abs(E).max() < 1e-14, (C, M)
+
+
 @pytest.mark.parametrize("dx,cells,k", [(1, [6, 8], 3), (2, [3, 2, 4, 3], 2)])
 def test_vp_steps_conserve_mass(dx, cells, k):
     vp = _vp(dx, cells, k, 3, L=2 * np.pi)
