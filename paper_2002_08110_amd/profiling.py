@@ -130,7 +130,9 @@ def trace(stats_csv, command, out_md):
         lines.append("| `%s` | %s | %.4f | %.4f | %.4f | %.2f |" % (
             r["Name"][:90], r["Calls"], float(r["AverageNs"]) / 1e6, float(r["MinNs"]) / 1e6,
             float(r["MaxNs"]) / 1e6, float(r["Percentage"])))
-    lines += ["", "Kernel source digest: `%s`." % kernel_source_digest()]
+    vp = hashlib.sha256(open(os.path.join(HERE, "csrc/hd_vp.hip"), "rb").read()).hexdigest()[:16]
+    lines += ["", "Kernel source digest: `%s` (stage kernels), `%s` (Vlasov-Poisson field)."
+              % (kernel_source_digest(), vp)]
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
 
