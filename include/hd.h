@@ -206,7 +206,11 @@ hd_status hd_apply(hd_solver *s, const double *in_dev, void *out_dev, hd_stream 
 hd_status hd_stable_dt(const hd_solver *s, double cfl, double *dt);
 
 /* One stage (stage = 0..4) of the low-storage RK scheme (Sec. 5.4), fused
- * into one pass: du <- A_s du + dt M^{-1}A(u); u <- u + B_s du. */
+ * into one pass: du <- A_s du + dt M^{-1}A(u); u <- u + B_s du. Stages
+ * 1..4 continue the step that stage 0 began: they read du, and under the
+ * Vlasov-Poisson field with the 6D degree-3 kernel they take the density
+ * from the velocity moments that the previous stage's kernel wrote with its
+ * output (stage 0 always integrates the state itself). */
 hd_status hd_rk_stage(hd_solver *s, int stage, double dt, hd_stream stream);
 
 /* nsteps full RK steps (5 fused stages each), replayed from a hipGraph

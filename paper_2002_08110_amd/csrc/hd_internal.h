@@ -39,7 +39,11 @@ struct hd_solver {
   // Vlasov-Poisson field (field_kind 2): modes per dimension and scratch.
   int vp_modes = 0, vp_groups = 0;
   size_t off_vp_partial = 0, off_vp_wv = 0, off_vp_A = 0, off_vp_B = 0, off_vp_Eh = 0,
-         off_vp_mats = 0;
+         off_vp_mats = 0, off_vp_mom = 0;
+  // Velocity moments written by the 6D degree-3 stage kernel (vp_mom_bytes
+  // > 0 for such solvers) and the solution buffer they describe (null: none).
+  size_t vp_mom_bytes = 0;
+  const double *vp_mom_src = nullptr;
 
   double *u(int i) const { return reinterpret_cast<double *>(ws + off_u[i]); }
   void *du() const { return ws + off_du; }
@@ -51,6 +55,7 @@ struct hd_solver {
   double2 *vp_bufB() const { return reinterpret_cast<double2 *>(ws + off_vp_B); }
   double2 *vp_Ehat() const { return reinterpret_cast<double2 *>(ws + off_vp_Eh); }
   double2 *vp_mats() const { return reinterpret_cast<double2 *>(ws + off_vp_mats); }
+  double *vp_mom() const { return reinterpret_cast<double *>(ws + off_vp_mom); }
   size_t psize() const { return prec == HD_FP32 ? sizeof(float) : sizeof(double); }
 };
 
@@ -94,7 +99,9 @@ hd_status enqueue_step(hd_solver *s, int par, double dt, hipStream_t st);
 constexpr int kVpMaxModes = 16;
 size_t vp_layout(hd_solver *s, size_t off);
 hd_status vp_upload(hd_solver *s);
-hd_status vp_enqueue(hd_solver *s, const double *u, hipStream_t st);
+// moments = true: the density from the stage kernel's velocity moments of u
+// (valid only when s->vp_mom_src == u), else from u itself.
+hd_status vp_enqueue(hd_solver *s, const double *u, hipStream_t st, bool moments = false);
 
 // Kernel parameters of a solver (everything but the per-launch fields:
 // buffers, mode, RK coefficients, dt). kernel = 1 passes constant fields in
@@ -116,6 +123,7 @@ void fill_params(const hd_solver *s, StageParams<P> *prm, int kernel) {
     prm->vh[j] = (P)s->h[j];
   }
   for (int m = 0; m < s->n; ++m) prm->xi[m] = (P)s->tab.xi[m];
+  for (int m = 0; m < s->n; ++m) prm->gw[m] = s->tab.w[m];
   for (int q = 0; q < s->n * s->n; ++q) prm->Dm[q] = (P)s->tab.D[q];
   // The Vlasov-Poisson field (kind 2) is a phase-space field whose E table
   // is recomputed before each stage.

@@ -276,9 +276,14 @@ hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, in
   const void *fn = hd::rt::stage_entry(s);
   if (!fn) return fail(HD_ERR_HIP, "no compiled stage kernel for this plan");
   if (s->field_kind == 2) {
-    // the Vlasov-Poisson field of this stage's input, into the E table
-    const hd_status vr = hd::rt::vp_enqueue(s, in, st);
+    // The Vlasov-Poisson field of this stage's input, into the E table. The
+    // first stage of a step reads the state; later stages take the density
+    // from the velocity moments the previous stage's kernel wrote with its
+    // output (so a captured step does not depend on what preceded it).
+    const bool moments = mode == 1 && stage > 0 && s->vp_mom_src == in;
+    const hd_status vr = hd::rt::vp_enqueue(s, in, st, moments);
     if (vr != HD_OK) return vr;
+    if (mode == 1 && s->plan.kernel == 1 && s->vp_mom_bytes) prm.vp_mom = s->vp_mom();
   }
   if (ls.shmem > 65536) {
     hipError_t ae = allow_large_lds(fn);
@@ -288,6 +293,7 @@ hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, in
   void *args[] = {&prm};
   hipError_t e = hipLaunchKernel(fn, dim3(ls.grid), dim3(ls.block), args, ls.shmem, st);
   if (e != hipSuccess) return fail(HD_ERR_HIP, std::string("stage kernel launch: ") + hipGetErrorString(e));
+  if (mode == 1) s->vp_mom_src = prm.vp_mom ? u_out : nullptr;
   return HD_OK;
 }
 
@@ -313,6 +319,7 @@ void drop_graphs(hd_solver *s) {
 void changed(hd_solver *s) {
   drop_graphs(s);
   ++s->version;
+  s->vp_mom_src = nullptr;
 }
 
 hd_status check_bound(const hd_solver *s) {
@@ -690,6 +697,7 @@ hd_status hd_set_state(hd_solver *s, const double *u, int u_is_device, hd_stream
   hd_status r = check_bound(s);
   if (r) return r;
   if (!u) return fail(HD_ERR_INVALID, "NULL state");
+  s->vp_mom_src = nullptr;
   HD_HIP(hipMemcpyAsync(s->u(s->cur), u, sizeof(double) * (size_t)s->ndofs,
                         u_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                         (hipStream_t)stream));
@@ -701,6 +709,7 @@ hd_status hd_init_state(hd_solver *s, int kind, const double *params, hd_stream 
   if (r) return r;
   if (kind != 0 && kind != 1) return fail(HD_ERR_INVALID, "initial state kind must be 0 or 1");
   const double alpha = (kind == 1 && params) ? params[0] : 0.0;
+  s->vp_mom_src = nullptr;
   const GeomArgs g = geom_of(s);
   const unsigned blocks = (unsigned)((s->ndofs + 255) / 256);
   hipLaunchKernelGGL(init_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, g, kind, alpha,

@@ -46,9 +46,14 @@ __device__ inline double2 cmul(double2 a, double2 b) {
 }
 
 // Pass 1 of the density: partial[g][p] = sum over the v-cells of group g and
-// all v-nodes of wv[vnode] * f (wv = product of the velocity GL weights).
-__global__ void vp_density_partial(VpGeom g, const double *__restrict__ u,
-                                   const double *__restrict__ wv, double *__restrict__ partial) {
+// r < R of wts[r] * src[cell * cstride + xnode + nxn * r]. From the state:
+// cstride = n^d, R = all v-nodes, wts = products of the velocity GL weights.
+// From the stage kernel's moments (already summed over the last two
+// velocity dimensions): cstride = 256, R = n (the first velocity node), wts =
+// the GL weights.
+__global__ void vp_density_partial(VpGeom g, const double *__restrict__ src, long long cstride,
+                                   int R, const double *__restrict__ wts,
+                                   double *__restrict__ partial) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= g.npts * g.groups) return;
   const long long p = idx % g.npts, grp = idx / g.npts;
@@ -56,8 +61,8 @@ __global__ void vp_density_partial(VpGeom g, const double *__restrict__ u,
   const long long c0 = grp * g.nvc / g.groups, c1 = (grp + 1) * g.nvc / g.groups;
   double s = 0.0;
   for (long long cv = c0; cv < c1; ++cv) {
-    const double *cellu = u + (xc + g.nxc * cv) * g.nd + xn;
-    for (long long vn = 0; vn < g.nvn; ++vn) s += wv[vn] * cellu[g.nxn * vn];
+    const double *cellu = src + (xc + g.nxc * cv) * cstride + xn;
+    for (int r = 0; r < R; ++r) s += wts[r] * cellu[g.nxn * r];
   }
   partial[grp * g.npts + p] = s;
 }
@@ -206,7 +211,7 @@ size_t vp_layout(hd_solver *s, size_t off) {
   s->off_vp_partial = off;
   off = up(off + (size_t)(g * npts) * sizeof(double));
   s->off_vp_wv = off;
-  off = up(off + (size_t)nvn * sizeof(double));
+  off = up(off + (size_t)(nvn + s->n) * sizeof(double));
   s->off_vp_A = off;
   off = up(off + (size_t)big * sizeof(double2));
   s->off_vp_B = off;
@@ -215,6 +220,10 @@ size_t vp_layout(hd_solver *s, size_t off) {
   off = up(off + (size_t)(s->dx * nm) * sizeof(double2));
   s->off_vp_mats = off;
   off = up(off + (size_t)mats * sizeof(double2));
+  // one moment per thread and cell of the 6D degree-3 kernel
+  s->vp_mom_bytes = k3_eligible(s) ? (size_t)s->ncells * 256 * sizeof(double) : 0;
+  s->off_vp_mom = off;
+  off = up(off + s->vp_mom_bytes);
   return off;
 }
 
@@ -232,6 +241,7 @@ hd_status vp_upload(hd_solver *s) {
     }
     wv[(size_t)vn] = w;
   }
+  for (int i = 0; i < s->n; ++i) wv.push_back(s->tab.w[i]);
   std::vector<double2> mats;
   for (int j = 0; j < s->dx; ++j) {
     const double kf = 2.0 * M_PI / (s->mesh.hi[j] - s->mesh.lo[j]);
@@ -258,12 +268,19 @@ hd_status vp_upload(hd_solver *s) {
 }
 
 // Enqueue steps 1-5 for the state `u` on `st`, writing the E table.
-hd_status vp_enqueue(hd_solver *s, const double *u, hipStream_t st) {
+hd_status vp_enqueue(hd_solver *s, const double *u, hipStream_t st, bool moments) {
   const VpGeom g = geom_of(s);
   double2 *A = s->vp_bufA(), *B = s->vp_bufB(), *Eh = s->vp_Ehat();
   const double2 *mats = s->vp_mats();
-  hipLaunchKernelGGL(vp_density_partial, dim3(blocks_for(g.npts * g.groups)), dim3(kVpThreads), 0,
-                     st, g, u, s->vp_wv(), s->vp_partial());
+  if (moments && (s->vp_mom_src != u || !s->vp_mom_bytes))
+    return fail(HD_ERR_STATE, "velocity moments do not describe this state");
+  if (moments)
+    hipLaunchKernelGGL(vp_density_partial, dim3(blocks_for(g.npts * g.groups)), dim3(kVpThreads),
+                       0, st, g, s->vp_mom(), (long long)g.nxn * s->n, s->n,
+                       s->vp_wv() + g.nvn, s->vp_partial());
+  else
+    hipLaunchKernelGGL(vp_density_partial, dim3(blocks_for(g.npts * g.groups)), dim3(kVpThreads),
+                       0, st, g, u, (long long)g.nd, (int)g.nvn, s->vp_wv(), s->vp_partial());
   hipLaunchKernelGGL(vp_density_final, dim3(blocks_for(g.npts)), dim3(kVpThreads), 0, st, g,
                      s->vp_partial(), A);
   // forward: axis 1 (A -> B), axis 2 (B -> A), axis 3 (A -> B); sizes as

@@ -373,14 +373,22 @@ __device__ __forceinline__ void stage_k3_body(const StageParams<P> &prm, unsigne
     for (int s = 0; s < 16; ++s) st_opt<NT>(ducell + t + 256 * s, dv[s]);
   }
   double *uocell = prm.u_out + (uint64_t)cell * ND;
+  double mom = 0.0, mrow = 0.0;
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
     double uo;
     if constexpr (sizeof(P) == sizeof(double)) uo = (double)u[s];
     else if constexpr (KEEPU) uo = ud[s];
     else uo = ucell[t + 256 * s];
-    st_opt<NT>(uocell + t + 256 * s, uo + prm.rk_b * (double)dv[s]);
+    const double un = uo + prm.rk_b * (double)dv[s];
+    st_opt<NT>(uocell + t + 256 * s, un);
+    mrow += prm.gw[s & 3] * un;
+    if ((s & 3) == 3) {
+      mom += prm.gw[s >> 2] * mrow;
+      mrow = 0.0;
+    }
   }
+  if (prm.vp_mom) prm.vp_mom[(uint64_t)cell * 256 + t] = mom;
 }
 
 template <typename P, int OPT>

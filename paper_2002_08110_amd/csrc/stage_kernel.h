@@ -74,6 +74,12 @@ struct StageParams {
   P xi[kMaxN];
   P Dm[kMaxN * kMaxN];  // Dm[q * N + m] = l'_m(xi_q) on [0, 1]
   P esign;
+  // Stage mode of the 6D degree-3 kernel under the Vlasov-Poisson field:
+  // per thread, the velocity moment of its 16 output values over (i5, i6),
+  // sum_i6 gw[i6] sum_i5 gw[i5] u_out, at vp_mom[cell * 256 + thread]; null
+  // otherwise.
+  double *vp_mom;
+  double gw[kMaxN];     // Gauss-Lobatto weights on [0, 1]
 };
 
 // Map the hardware workgroup id (dispatched round-robin over the 8 XCDs) to a

@@ -153,15 +153,22 @@ def test_stable_dt_matches_oracle(dx, cells, k, modes):
     S.close()
 
 
-def test_graph_replay_is_bitwise_equal_to_direct_stages():
-    case = vp_case(2, [3, 2, 2, 3], 3, 3)
+@pytest.mark.parametrize("dx,cells,plan", [
+    (2, [3, 2, 2, 3], None),
+    # 6D degree 3: later stages take the density from the kernel's moments
+    (3, [2, 1, 2, 2, 1, 2], dict(kernel=1, reg_dims=2, options=1, xcd_remap=1)),
+    (3, [2, 1, 2, 2, 1, 2], dict(kernel=0, reg_dims=2, lds=1, options=0, xcd_remap=1))])
+def test_graph_replay_is_bitwise_equal_to_direct_stages(dx, cells, plan):
+    case = vp_case(dx, cells, 3, 2)
     u0 = _state(case, 26)
-    A = gpu_solver(case, "fp64")
-    B = gpu_solver(case, "fp64")
+    A = gpu_solver(case, "fp64", plan=plan)
+    B = gpu_solver(case, "fp64", plan=plan)
     A.set_state(u0)
     B.set_state(u0)
     torch.cuda.synchronize()
     dt = A.stable_dt(0.2)
+    V = oracle_problem(case)
+    ref = V.rk_steps(u0, dt, 6)
     for rep in range(3):
         A.rk_step(dt, 2)
         for _ in range(2):
@@ -169,6 +176,7 @@ def test_graph_replay_is_bitwise_equal_to_direct_stages():
                 B.rk_stage(st, dt)
         torch.cuda.synchronize()
         assert np.array_equal(A.get_state(), B.get_state()), rep
+    assert rel_l2(A.get_state(), ref) <= TOL_FP64
     A.close()
     B.close()
 
