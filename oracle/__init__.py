@@ -54,6 +54,7 @@ def _load():
         d = ctypes.c_double
         i64 = ctypes.c_int64
         lib.or_gl_rule.argtypes = [ctypes.c_int, P(d), P(d)]
+        lib.or_gauss_rule.argtypes = [ctypes.c_int, P(d), P(d)]
         lib.or_lagrange.argtypes = [ctypes.c_int, P(d), ctypes.c_int, d]
         lib.or_lagrange.restype = d
         lib.or_lagrange_deriv.argtypes = [ctypes.c_int, P(d), ctypes.c_int, d]
@@ -300,6 +301,16 @@ def gl_rule(k):
     if lib.or_gl_rule(k, _dp(xi), _dp(w)):
         raise ValueError(k)
     return xi, w
+
+
+def gauss_rule(k):
+    """Gauss-Legendre points and weights (k+1 of them) on [0, 1]."""
+    lib = _load()
+    g = np.zeros(k + 1)
+    w = np.zeros(k + 1)
+    if lib.or_gauss_rule(k, _dp(g), _dp(w)):
+        raise ValueError(k)
+    return g, w
 
 
 def lagrange(k, xi, m, x):

@@ -81,6 +81,29 @@ int or_gl_rule(int k, double *xi, double *w) {
   return 0;
 }
 
+/* 1D Gauss-Legendre rule with k+1 points on [0,1] (the quadrature the paper
+ * uses by default, Sec. 2.5 and 5.1): the roots s of P_{k+1}, by Newton's
+ * method from the estimates -cos(pi (m + 3/4) / (n + 1/2)), and the weights
+ * 2 / ((1 - s^2) P_{k+1}'(s)^2) on [-1,1], halved for [0,1]. */
+int or_gauss_rule(int k, double *g, double *w) {
+  if (k < 1 || k > 16) return -1;
+  const int n = k + 1;
+  for (int m = 0; m < n; ++m) {
+    double x = -cos(OR_PI * (m + 0.75) / (n + 0.5));
+    double p = 0.0, dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      legendre(n, x, &p, &dp);
+      double dx = p / dp;
+      x -= dx;
+      if (fabs(dx) < 1e-16) break;
+    }
+    legendre(n, x, &p, &dp);
+    g[m] = 0.5 * (1.0 + x);
+    w[m] = 1.0 / ((1.0 - x * x) * dp * dp);
+  }
+  return 0;
+}
+
 /* l_m(x) = prod_{r != m} (x - xi_r) / (xi_m - xi_r). */
 double or_lagrange(int k, const double *xi, int m, double x) {
   double v = 1.0;
@@ -118,7 +141,43 @@ typedef struct {
   double L[OR_MAXN][OR_MAXN];  /* L[m][q] = l_m(xi_q) */
   double DL[OR_MAXN][OR_MAXN]; /* DL[m][q] = l_m'(xi_q) */
   double M1[OR_MAXN];          /* diagonal of the 1D reference mass matrix */
+  /* Gauss-Legendre quadrature (mode 2): points, weights, the GL basis and
+   * its derivative at the points, and the 1D mass matrix it integrates
+   * exactly, MG[a][b] = sum_q wg_q l_a(g_q) l_b(g_q), with its inverse. */
+  double gq[OR_MAXN], wg[OR_MAXN];
+  double LG[OR_MAXN][OR_MAXN];  /* LG[m][q] = l_m(g_q) */
+  double DLG[OR_MAXN][OR_MAXN]; /* DLG[m][q] = l_m'(g_q) */
+  double MG[OR_MAXN][OR_MAXN], MGinv[OR_MAXN][OR_MAXN];
 } or_geom;
+
+/* Inverse of the n x n matrix A by Gauss-Jordan elimination with partial
+ * pivoting; returns -1 if A is singular. */
+static int invert(int n, double A[OR_MAXN][OR_MAXN], double X[OR_MAXN][OR_MAXN]) {
+  double T[OR_MAXN][2 * OR_MAXN];
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < 2 * n; ++c) T[r][c] = c < n ? A[r][c] : (c - n == r ? 1.0 : 0.0);
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (fabs(T[r][c]) > fabs(T[piv][c])) piv = r;
+    if (T[piv][c] == 0.0) return -1;
+    for (int q = 0; q < 2 * n; ++q) {
+      double t = T[c][q];
+      T[c][q] = T[piv][q];
+      T[piv][q] = t;
+    }
+    double inv = 1.0 / T[c][c];
+    for (int q = 0; q < 2 * n; ++q) T[c][q] *= inv;
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      double f = T[r][c];
+      for (int q = 0; q < 2 * n; ++q) T[r][q] -= f * T[c][q];
+    }
+  }
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < n; ++c) X[r][c] = T[r][n + c];
+  return 0;
+}
 
 static int setup_geom(const or_mesh *mesh, int k, or_geom *g) {
   if (!mesh) return -1;
@@ -163,6 +222,19 @@ static int setup_geom(const or_mesh *mesh, int k, or_geom *g) {
       else if (fabs(m) > 1e-14)
         return -1;
     }
+  if (or_gauss_rule(k, g->gq, g->wg)) return -1;
+  for (int m = 0; m <= k; ++m)
+    for (int q = 0; q <= k; ++q) {
+      g->LG[m][q] = or_lagrange(k, g->xi, m, g->gq[q]);
+      g->DLG[m][q] = or_lagrange_deriv(k, g->xi, m, g->gq[q]);
+    }
+  for (int a = 0; a <= k; ++a)
+    for (int b = 0; b <= k; ++b) {
+      double m = 0.0;
+      for (int q = 0; q <= k; ++q) m += g->wg[q] * g->LG[a][q] * g->LG[b][q];
+      g->MG[a][b] = m;
+    }
+  if (invert(g->n, g->MG, g->MGinv)) return -1;
   return 0;
 }
 
@@ -396,12 +468,153 @@ static void eval_cell(const or_geom *g, const or_field *f, int mode,
   }
 }
 
+/* ------------------------------------------------------------------------ */
+/* The same operator with Gauss-Legendre quadrature (mode 2; Sec. 2.5)       */
+/* ------------------------------------------------------------------------ */
+
+/* Field component j at the Gauss point qm of cell cm (qm indexes Gauss
+ * points; for a face point the normal index is ignored by the field, which
+ * does not depend on the coordinate along its own component). a_{x_j} is the
+ * velocity coordinate at the Gauss point; a_{v_j} is sign times the nodal
+ * interpolant of the E table in the x-cell, evaluated at the x-point. */
+static double field_at_gauss(const or_geom *g, const or_field *f, const int *cm,
+                             const int *qm, int j) {
+  if (f->kind == 0) return f->a[j];
+  if (j < g->dx) {
+    const int vj = g->dx + j;
+    return g->lo[vj] + (cm[vj] + g->gq[qm[vj]]) * g->h[vj];
+  }
+  int64_t xcell = 0, xs = 1, nxn = 1;
+  for (int m = 0; m < g->dx; ++m) {
+    xcell += cm[m] * xs;
+    xs *= g->cells[m];
+    nxn *= g->n;
+  }
+  double e = 0.0;
+  int xm[OR_MAXD];
+  for (int64_t xn = 0; xn < nxn; ++xn) {
+    int64_t r = xn;
+    double ph = 1.0;
+    for (int m = 0; m < g->dx; ++m) {
+      xm[m] = (int)(r % g->n);
+      r /= g->n;
+      ph *= g->LG[xm[m]][qm[m]];
+    }
+    e += f->E[((xcell * nxn) + xn) * g->dx + (j - g->dx)] * ph;
+  }
+  return f->sign * e;
+}
+
+/* phi_i at the Gauss point qm: prod_m l_{i_m}(g_{q_m}). */
+static double phi_gauss(const or_geom *g, const int *im, const int *qm) {
+  double v = 1.0;
+  for (int m = 0; m < g->d; ++m) v *= g->LG[im[m]][qm[m]];
+  return v;
+}
+
+/* The weak form of Sec. 1.3 with every integral taken by the tensor
+ * Gauss-Legendre rule of k+1 points per dimension: volume points g_q, face
+ * points the Gauss points in the d-1 tangential dimensions, and the mass
+ * matrix this rule integrates exactly, the Kronecker product of h_j MG. */
+static void eval_cell_gauss(const or_geom *g, const or_field *f, const double *u,
+                            int64_t c, double *out, or_scratch *s) {
+  const int d = g->d, k = g->k;
+  const int64_t nd = g->nd;
+  int cm[OR_MAXD], im[OR_MAXD], qm[OR_MAXD];
+  cell_multi(g, c, cm);
+  const double *uc = u + c * nd;
+
+  /* u_h and a at the cell's Gauss points */
+  for (int64_t q = 0; q < nd; ++q) {
+    node_multi(g, q, qm);
+    double v = 0.0;
+    for (int64_t ip = 0; ip < nd; ++ip) {
+      node_multi(g, ip, im);
+      v += uc[ip] * phi_gauss(g, im, qm);
+    }
+    s->uh[q] = v;
+    for (int j = 0; j < d; ++j) s->acell[q * d + j] = field_at_gauss(g, f, cm, qm, j);
+  }
+
+  /* V_i = sum_q W_q grad phi_i(g_q) . a(g_q) u_h(g_q), W_q = prod h_m wg_{q_m} */
+  for (int64_t i = 0; i < nd; ++i) {
+    node_multi(g, i, im);
+    double v = 0.0;
+    for (int64_t q = 0; q < nd; ++q) {
+      node_multi(g, q, qm);
+      double W = 1.0;
+      for (int m = 0; m < d; ++m) W *= g->h[m] * g->wg[qm[m]];
+      for (int j = 0; j < d; ++j) {
+        double dphi = g->DLG[im[j]][qm[j]] / g->h[j];
+        for (int m = 0; m < d; ++m)
+          if (m != j) dphi *= g->LG[im[m]][qm[m]];
+        v += W * dphi * s->acell[q * d + j] * s->uh[q];
+      }
+    }
+    s->rhs[i] = v;
+  }
+
+  /* F_i = sum over faces and face Gauss points p of W^f_p phi_i(p) (a.n) u*,
+   * upwind u*. On the face xi_j = 0 (side 0) or 1 (side 1) only the nodes
+   * with i_j on that face have nonzero phi (nodal basis). */
+  for (int j = 0; j < d; ++j)
+    for (int side = 0; side < 2; ++side) {
+      const int pj = side ? k : 0;
+      const int oj = side ? 0 : k;
+      const double nj = side ? 1.0 : -1.0;
+      const int64_t cn = neighbour_cell(g, cm, j, side ? +1 : -1);
+      const double *un = u + cn * nd;
+      for (int64_t p = 0; p < nd; ++p) {
+        node_multi(g, p, qm);
+        if (qm[j] != 0) continue; /* one pass over the tangential Gauss points */
+        double uown = 0.0, unbr = 0.0;
+        for (int64_t ip = 0; ip < nd; ++ip) {
+          node_multi(g, ip, im);
+          double ph = 1.0;
+          for (int m = 0; m < d; ++m)
+            if (m != j) ph *= g->LG[im[m]][qm[m]];
+          if (im[j] == pj) uown += uc[ip] * ph;
+          if (im[j] == oj) unbr += un[ip] * ph;
+        }
+        const double an = field_at_gauss(g, f, cm, qm, j) * nj;
+        const double ustar = (an >= 0.0) ? uown : unbr;
+        double Wf = 1.0;
+        for (int m = 0; m < d; ++m)
+          if (m != j) Wf *= g->h[m] * g->wg[qm[m]];
+        for (int64_t i = 0; i < nd; ++i) {
+          node_multi(g, i, im);
+          if (im[j] != pj) continue;
+          double ph = 1.0;
+          for (int m = 0; m < d; ++m)
+            if (m != j) ph *= g->LG[im[m]][qm[m]];
+          s->rhs[i] -= Wf * ph * an * ustar;
+        }
+      }
+    }
+
+  /* Inverse mass: the inverse of a Kronecker product is the Kronecker
+   * product of the inverses, applied one dimension at a time. */
+  for (int64_t i = 0; i < nd; ++i) out[i] = s->rhs[i];
+  double line[OR_MAXN];
+  for (int j = 0; j < d; ++j)
+    for (int64_t b = 0; b < nd; ++b) {
+      node_multi(g, b, im);
+      if (im[j] != 0) continue;
+      for (int r = 0; r <= k; ++r) line[r] = out[b + r * g->nstride[j]];
+      for (int r = 0; r <= k; ++r) {
+        double v = 0.0;
+        for (int q = 0; q <= k; ++q) v += g->MGinv[r][q] * line[q];
+        out[b + r * g->nstride[j]] = v / g->h[j];
+      }
+    }
+}
+
 int or_apply_cells(const or_mesh *mesh, int k, const or_field *field, int mode,
                    const double *u, const int64_t *cells, int64_t ncells,
                    double *out) {
   or_geom g;
   if (setup_geom(mesh, k, &g) || check_field(&g, field)) return -1;
-  if (mode != 0 && mode != 1) return -1;
+  if (mode < 0 || mode > 2) return -1;
   for (int64_t t = 0; t < ncells; ++t)
     if (cells[t] < 0 || cells[t] >= g.ncells) return -1;
   int err = 0;
@@ -416,8 +629,12 @@ int or_apply_cells(const or_mesh *mesh, int k, const or_field *field, int mode,
       err = 1;
     } else {
 #pragma omp for schedule(dynamic, 4)
-      for (int64_t t = 0; t < ncells; ++t)
-        eval_cell(&g, field, mode, u, cells[t], out + t * g.nd, &s);
+      for (int64_t t = 0; t < ncells; ++t) {
+        if (mode == 2)
+          eval_cell_gauss(&g, field, u, cells[t], out + t * g.nd, &s);
+        else
+          eval_cell(&g, field, mode, u, cells[t], out + t * g.nd, &s);
+      }
     }
     free(s.uh);
     free(s.rhs);

@@ -73,10 +73,17 @@ int64_t or_num_dofs(const or_mesh *mesh, int k);
  * (dof = cell * n^d + node, cell and node lexicographic, dim 1 fastest). */
 int or_node_coords(const or_mesh *mesh, int k, double *X);
 
+/* Gauss-Legendre rule with k+1 points on [0,1]; g ascending, sum w = 1. */
+int or_gauss_rule(int k, double *g, double *w);
+
 /* Evaluate out = M^{-1} A(u) for the listed cells (out holds n^d values per
  * listed cell, in list order). mode 0: full basis (every phi_i evaluated at
  * every quadrature point); mode 1: the same sums with structurally zero
- * basis values skipped. Returns 0, or -1 on invalid input. */
+ * basis values skipped; mode 2: the same weak form with Gauss-Legendre
+ * quadrature (k+1 points per dimension, full sums, the exactly integrated
+ * non-diagonal mass matrix; the E table enters through its nodal
+ * interpolant). Every function taking a mode accepts 2. Returns 0, or -1 on
+ * invalid input. */
 int or_apply_cells(const or_mesh *mesh, int k, const or_field *field, int mode,
                    const double *u, const int64_t *cells, int64_t ncells,
                    double *out);
