@@ -173,6 +173,19 @@ hd_status hd_set_field_vlasov_poisson(hd_solver *s, int modes);
  * hd_bind and dim_x == dim_v. */
 hd_status hd_get_field(hd_solver *s, double *E_host, hd_stream stream);
 
+/* Quadrature of the DG integrals (Sec. 2.5): 0 = Gauss-Lobatto points
+ * collocated with the nodes (diagonal mass matrix; the default), 1 =
+ * Gauss-Legendre with k+1 points per dimension, the paper's default (the
+ * exactly integrated mass matrix, applied through the basis change to the
+ * Gauss points and back; a_v = E enters through the nodal interpolant of
+ * the E table). The nodal GL basis and the state layout are the same for
+ * both. Quadrature 1 runs one cell per workgroup with the cell and two face
+ * layers in LDS and returns HD_ERR_UNSUPPORTED where those exceed 160 KiB
+ * (FP64 6D degree >= 4, FP32 6D degree 5; FP64 5D degree 5 is not
+ * compiled either). Launch plans apply to
+ * quadrature 0 only. */
+hd_status hd_set_quadrature(hd_solver *s, int quadrature);
+
 /* For the Vlasov-Poisson field: recompute the device E table from the
  * current state on `stream` (Sec. 6, steps 1-4 of a stage; asynchronous).
  * A no-op for prescribed fields. Requires hd_bind. */

@@ -353,6 +353,7 @@ typedef struct {
   double *uh;   /* u_h at the quadrature points of the cell */
   double *rhs;  /* V - F, then divided by the mass diagonal */
   double *acell; /* a_j at each node: acell[q * d + j] */
+  int *multi;    /* multi-index of every node: multi[q * d + m] (mode 2) */
 } or_scratch;
 
 static void eval_cell(const or_geom *g, const or_field *f, int mode,
@@ -523,33 +524,39 @@ static void eval_cell_gauss(const or_geom *g, const or_field *f, const double *u
   int cm[OR_MAXD], im[OR_MAXD], qm[OR_MAXD];
   cell_multi(g, c, cm);
   const double *uc = u + c * nd;
+  for (int64_t q = 0; q < nd; ++q) node_multi(g, q, s->multi + q * d);
 
   /* u_h and a at the cell's Gauss points */
   for (int64_t q = 0; q < nd; ++q) {
-    node_multi(g, q, qm);
+    memcpy(qm, s->multi + q * d, sizeof(int) * d);
     double v = 0.0;
     for (int64_t ip = 0; ip < nd; ++ip) {
-      node_multi(g, ip, im);
+      memcpy(im, s->multi + ip * d, sizeof(int) * d);
       v += uc[ip] * phi_gauss(g, im, qm);
     }
     s->uh[q] = v;
     for (int j = 0; j < d; ++j) s->acell[q * d + j] = field_at_gauss(g, f, cm, qm, j);
   }
 
-  /* V_i = sum_q W_q grad phi_i(g_q) . a(g_q) u_h(g_q), W_q = prod h_m wg_{q_m} */
+  /* V_i = sum_q W_q grad phi_i(g_q) . a(g_q) u_h(g_q), W_q = prod h_m wg_{q_m};
+   * d/dx_j phi_i = l'_{i_j} / h_j times the product of the other factors,
+   * taken as prefix times suffix product. */
   for (int64_t i = 0; i < nd; ++i) {
-    node_multi(g, i, im);
+    memcpy(im, s->multi + i * d, sizeof(int) * d);
     double v = 0.0;
     for (int64_t q = 0; q < nd; ++q) {
-      node_multi(g, q, qm);
+      memcpy(qm, s->multi + q * d, sizeof(int) * d);
       double W = 1.0;
       for (int m = 0; m < d; ++m) W *= g->h[m] * g->wg[qm[m]];
-      for (int j = 0; j < d; ++j) {
-        double dphi = g->DLG[im[j]][qm[j]] / g->h[j];
-        for (int m = 0; m < d; ++m)
-          if (m != j) dphi *= g->LG[im[m]][qm[m]];
-        v += W * dphi * s->acell[q * d + j] * s->uh[q];
-      }
+      double pre[OR_MAXD + 1], suf[OR_MAXD + 1];
+      pre[0] = 1.0;
+      for (int m = 0; m < d; ++m) pre[m + 1] = pre[m] * g->LG[im[m]][qm[m]];
+      suf[d] = 1.0;
+      for (int m = d - 1; m >= 0; --m) suf[m] = suf[m + 1] * g->LG[im[m]][qm[m]];
+      double div = 0.0;
+      for (int j = 0; j < d; ++j)
+        div += g->DLG[im[j]][qm[j]] / g->h[j] * pre[j] * suf[j + 1] * s->acell[q * d + j];
+      v += W * div * s->uh[q];
     }
     s->rhs[i] = v;
   }
@@ -565,11 +572,12 @@ static void eval_cell_gauss(const or_geom *g, const or_field *f, const double *u
       const int64_t cn = neighbour_cell(g, cm, j, side ? +1 : -1);
       const double *un = u + cn * nd;
       for (int64_t p = 0; p < nd; ++p) {
-        node_multi(g, p, qm);
+        memcpy(qm, s->multi + p * d, sizeof(int) * d);
         if (qm[j] != 0) continue; /* one pass over the tangential Gauss points */
         double uown = 0.0, unbr = 0.0;
         for (int64_t ip = 0; ip < nd; ++ip) {
-          node_multi(g, ip, im);
+          memcpy(im, s->multi + ip * d, sizeof(int) * d);
+          if (im[j] != pj && im[j] != oj) continue; /* zero on both faces */
           double ph = 1.0;
           for (int m = 0; m < d; ++m)
             if (m != j) ph *= g->LG[im[m]][qm[m]];
@@ -582,7 +590,7 @@ static void eval_cell_gauss(const or_geom *g, const or_field *f, const double *u
         for (int m = 0; m < d; ++m)
           if (m != j) Wf *= g->h[m] * g->wg[qm[m]];
         for (int64_t i = 0; i < nd; ++i) {
-          node_multi(g, i, im);
+          memcpy(im, s->multi + i * d, sizeof(int) * d);
           if (im[j] != pj) continue;
           double ph = 1.0;
           for (int m = 0; m < d; ++m)
@@ -598,7 +606,7 @@ static void eval_cell_gauss(const or_geom *g, const or_field *f, const double *u
   double line[OR_MAXN];
   for (int j = 0; j < d; ++j)
     for (int64_t b = 0; b < nd; ++b) {
-      node_multi(g, b, im);
+      memcpy(im, s->multi + b * d, sizeof(int) * d);
       if (im[j] != 0) continue;
       for (int r = 0; r <= k; ++r) line[r] = out[b + r * g->nstride[j]];
       for (int r = 0; r <= k; ++r) {
@@ -624,7 +632,8 @@ int or_apply_cells(const or_mesh *mesh, int k, const or_field *field, int mode,
     s.uh = (double *)malloc(sizeof(double) * g.nd);
     s.rhs = (double *)malloc(sizeof(double) * g.nd);
     s.acell = (double *)malloc(sizeof(double) * g.nd * g.d);
-    if (!s.uh || !s.rhs || !s.acell) {
+    s.multi = (int *)malloc(sizeof(int) * g.nd * g.d);
+    if (!s.uh || !s.rhs || !s.acell || !s.multi) {
 #pragma omp atomic write
       err = 1;
     } else {
@@ -639,6 +648,7 @@ int or_apply_cells(const or_mesh *mesh, int k, const or_field *field, int mode,
     free(s.uh);
     free(s.rhs);
     free(s.acell);
+    free(s.multi);
   }
   return err ? -1 : 0;
 }

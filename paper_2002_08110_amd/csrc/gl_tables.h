@@ -114,4 +114,137 @@ inline bool make_tables(int k, Tables1D *t) {
   return true;
 }
 
+// Gauss-Legendre variant (Sec. 2.5, the paper's default quadrature): n = k+1
+// points g_q with weights om_q on [0,1], and the matrices that move between
+// the GL nodal basis and values at the points.
+struct GaussTables1D {
+  int n = 0;
+  double g[8] = {0}, om[8] = {0};
+  double B[64] = {0};     // B[q * n + i] = l_i(g_q)
+  double Binv[64] = {0};  // B^{-1}
+  double Dg[64] = {0};    // derivative at g_q of the interpolant through the points
+  double ext[2][8] = {};  // ext[s][q] = Binv[s * k][q]: the trace at xi = s
+  double lift[2][8] = {}; // ext[s][q] / om_q
+};
+
+// Number of eigenvalues below x of the symmetric tridiagonal Jacobi matrix of
+// the Legendre polynomials on [-1,1] (zero diagonal, off-diagonal
+// m / sqrt(4 m^2 - 1)), by the Sturm sequence of its leading minors.
+inline int legendre_jacobi_count_below(int n, long double x) {
+  int count = 0;
+  long double q = -x;  // d_1 = a_1 - x with a_1 = 0
+  for (int i = 0;; ++i) {
+    if (q < 0) ++count;
+    if (i + 1 == n) break;
+    const long double m = (long double)(i + 1);
+    const long double b2 = m * m / (4.0L * m * m - 1.0L);
+    long double qq = q == 0.0L ? 1e-30L : q;
+    q = -x - b2 / qq;
+  }
+  return count;
+}
+
+inline bool make_gauss_tables(const Tables1D &gl, GaussTables1D *t) {
+  const int n = gl.n, k = n - 1;
+  if (n < 2 || n > 8) return false;
+  t->n = n;
+  // Points: the eigenvalues of the Jacobi matrix, one bisection per index.
+  long double s[8];
+  for (int m = 0; m < n; ++m) {
+    long double lo = -1.0L, hi = 1.0L;
+    for (int it = 0; it < 90; ++it) {
+      const long double mid = 0.5L * (lo + hi);
+      if (legendre_jacobi_count_below(n, mid) > m) hi = mid;
+      else lo = mid;
+    }
+    s[m] = 0.5L * (lo + hi);
+  }
+  long double g[8];
+  for (int m = 0; m < n; ++m) g[m] = 0.5L * (1.0L + s[m]);
+  // Weights from the moment conditions sum_m om_m g_m^p = 1/(p+1), p < n.
+  long double A[8][9];
+  for (int p = 0; p < n; ++p) {
+    for (int m = 0; m < n; ++m) A[p][m] = powl(g[m], p);
+    A[p][n] = 1.0L / (p + 1);
+  }
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (fabsl(A[r][col]) > fabsl(A[piv][col])) piv = r;
+    for (int c = 0; c <= n; ++c) {
+      const long double tmp = A[col][c];
+      A[col][c] = A[piv][c];
+      A[piv][c] = tmp;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      const long double f = A[r][col] / A[col][col];
+      for (int c = col; c <= n; ++c) A[r][c] -= f * A[col][c];
+    }
+  }
+  long double om[8];
+  for (int m = 0; m < n; ++m) om[m] = A[m][n] / A[m][m];
+  // Lagrange values and derivatives of the GL basis at the points (for even
+  // k the midpoint is both a point and a node, so no division by x - xi_r):
+  // l_i(x) = prod_{r != i} (x - xi_r) / (xi_i - xi_r),
+  // l_i'(x) = sum_{s != i} 1 / (xi_i - xi_s) prod_{r != i, s} (x - xi_r) / (xi_i - xi_r).
+  long double B[8][8], DB[8][8];
+  for (int q = 0; q < n; ++q)
+    for (int i = 0; i < n; ++i) {
+      const long double xq = g[q], xii = (long double)gl.xi[i];
+      long double v = 1.0L, dsum = 0.0L;
+      for (int r = 0; r < n; ++r)
+        if (r != i) v *= (xq - (long double)gl.xi[r]) / (xii - (long double)gl.xi[r]);
+      for (int sx = 0; sx < n; ++sx) {
+        if (sx == i) continue;
+        long double tm = 1.0L / (xii - (long double)gl.xi[sx]);
+        for (int r = 0; r < n; ++r)
+          if (r != i && r != sx) tm *= (xq - (long double)gl.xi[r]) / (xii - (long double)gl.xi[r]);
+        dsum += tm;
+      }
+      B[q][i] = v;
+      DB[q][i] = dsum;
+    }
+  // B^{-1} by Gauss-Jordan elimination with partial pivoting.
+  long double T[8][16];
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < 2 * n; ++c) T[r][c] = c < n ? B[r][c] : (c - n == r ? 1.0L : 0.0L);
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (fabsl(T[r][col]) > fabsl(T[piv][col])) piv = r;
+    if (T[piv][col] == 0.0L) return false;
+    for (int c = 0; c < 2 * n; ++c) {
+      const long double tmp = T[col][c];
+      T[col][c] = T[piv][c];
+      T[piv][c] = tmp;
+    }
+    const long double inv = 1.0L / T[col][col];
+    for (int c = 0; c < 2 * n; ++c) T[col][c] *= inv;
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      const long double f = T[r][col];
+      for (int c = 0; c < 2 * n; ++c) T[r][c] -= f * T[col][c];
+    }
+  }
+  for (int q = 0; q < n; ++q) {
+    t->g[q] = (double)g[q];
+    t->om[q] = (double)om[q];
+    for (int i = 0; i < n; ++i) {
+      t->B[q * n + i] = (double)B[q][i];
+      t->Binv[q * n + i] = (double)T[q][n + i];
+      long double dg = 0.0L;  // Dg = DB B^{-1}
+      for (int m = 0; m < n; ++m) dg += DB[q][m] * T[m][n + i];
+      t->Dg[q * n + i] = (double)dg;
+    }
+  }
+  for (int sd = 0; sd < 2; ++sd)
+    for (int q = 0; q < n; ++q) {
+      const long double e = T[sd * k][n + q];
+      t->ext[sd][q] = (double)e;
+      t->lift[sd][q] = (double)(e / om[q]);
+    }
+  return true;
+}
+
 }  // namespace hd

@@ -36,6 +36,10 @@ struct hd_solver {
   double gdt = 0.0;
   bool gvalid = false;
   uint64_t version = 0;  // bumped when the plan, field or memory changes
+  // Quadrature: 0 Gauss-Lobatto collocation, 1 Gauss-Legendre (k+1 points).
+  int quad = 0;
+  hd::GaussTables1D gtab{};
+  bool gtab_ok = false;
   // Vlasov-Poisson field (field_kind 2): modes per dimension and scratch.
   int vp_modes = 0, vp_groups = 0;
   size_t off_vp_partial = 0, off_vp_wv = 0, off_vp_A = 0, off_vp_B = 0, off_vp_Eh = 0,

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "hd_internal.h"
+#include "stage_gauss.h"
 #include "stage_dispatch.h"
 #include "stage_k3.h"
 
@@ -181,6 +182,12 @@ hd_plan default_plan(const hd_solver *s) {
 
 hd::LaunchShape hd::rt::shape_of(const hd_solver *s) {
   hd::LaunchShape ls{};
+  if (s->quad == 1) {
+    ls.grid = (unsigned)s->ncells;
+    ls.block = (unsigned)hd::gauss_threads((int)s->nd);
+    ls.shmem = (size_t)hd::gauss_lds_elems(s->d, s->n, s->dx) * s->psize();
+    return ls;
+  }
   if (s->plan.kernel == 1) {
     ls.grid = (unsigned)s->ncells;
     ls.block = 256;
@@ -211,6 +218,7 @@ namespace rt {
 
 const void *stage_entry(const hd_solver *s) {
   const bool f32 = s->prec == HD_FP32;
+  if (s->quad == 1) return hd::stage_gauss_entry(s->d, s->n, f32);
   if (s->plan.kernel == 1) return f32 ? hd::stage_k3_f32(s->plan.options)
                                       : hd::stage_k3_f64(s->plan.options);
   const int rd = s->plan.reg_dims, lds = s->plan.lds, n = s->n, sd = s->plan.split_dims,
@@ -283,14 +291,31 @@ hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, in
     const bool moments = mode == 1 && stage > 0 && s->vp_mom_src == in;
     const hd_status vr = hd::rt::vp_enqueue(s, in, st, moments);
     if (vr != HD_OK) return vr;
-    if (mode == 1 && s->plan.kernel == 1 && s->vp_mom_bytes) prm.vp_mom = s->vp_mom();
+    if (mode == 1 && s->quad == 0 && s->plan.kernel == 1 && s->vp_mom_bytes)
+      prm.vp_mom = s->vp_mom();
   }
   if (ls.shmem > 65536) {
     hipError_t ae = allow_large_lds(fn);
     if (ae != hipSuccess)
       return fail(HD_ERR_HIP, std::string("raising the LDS limit: ") + hipGetErrorString(ae));
   }
-  void *args[] = {&prm};
+  hd::GaussTables<P> gt;
+  void *args[] = {&prm, &gt};
+  if (s->quad == 1) {
+    const int n = s->n;
+    for (int q = 0; q < n * n; ++q) {
+      gt.B[q] = (P)s->gtab.B[q];
+      gt.Binv[q] = (P)s->gtab.Binv[q];
+      gt.Dg[q] = (P)s->gtab.Dg[q];
+    }
+    for (int q = 0; q < n; ++q) {
+      gt.g[q] = (P)s->gtab.g[q];
+      for (int sd = 0; sd < 2; ++sd) {
+        gt.ext[sd][q] = (P)s->gtab.ext[sd][q];
+        gt.lift[sd][q] = (P)s->gtab.lift[sd][q];
+      }
+    }
+  }
   hipError_t e = hipLaunchKernel(fn, dim3(ls.grid), dim3(ls.block), args, ls.shmem, st);
   if (e != hipSuccess) return fail(HD_ERR_HIP, std::string("stage kernel launch: ") + hipGetErrorString(e));
   if (mode == 1) s->vp_mom_src = prm.vp_mom ? u_out : nullptr;
@@ -543,6 +568,7 @@ hd_status hd_create(const hd_mesh *mesh, int degree, int prec, hd_solver **out) 
     delete s;
     return fail(HD_ERR_INVALID, "Gauss-Lobatto table construction failed");
   }
+  s->gtab_ok = hd::make_gauss_tables(s->tab, &s->gtab);
   int64_t nxc = 1, nxn = 1;
   for (int j = 0; j < s->dx; ++j) {
     nxc *= mesh->cells[j];
@@ -661,6 +687,22 @@ hd_status hd_set_field_vlasov_poisson(hd_solver *s, int modes) {
   s->esign = -1.0;
   s->vp_modes = modes;
   return upload_E(s);
+}
+
+hd_status hd_set_quadrature(hd_solver *s, int quadrature) {
+  if (!s) return fail(HD_ERR_INVALID, "NULL argument");
+  if (quadrature != 0 && quadrature != 1)
+    return fail(HD_ERR_INVALID, "quadrature must be 0 (Gauss-Lobatto) or 1 (Gauss-Legendre)");
+  if (quadrature == 1) {
+    if (!s->gtab_ok) return fail(HD_ERR_INVALID, "Gauss-Legendre table construction failed");
+    if (!hd::stage_gauss_entry(s->d, s->n, s->prec == HD_FP32))
+      return fail(HD_ERR_UNSUPPORTED,
+                  "the Gauss-Legendre kernel holds a cell and two face layers in LDS: this "
+                  "(d, degree, precision) exceeds 160 KiB");
+  }
+  s->quad = quadrature;
+  changed(s);
+  return HD_OK;
 }
 
 hd_status hd_compute_field(hd_solver *s, hd_stream stream) {

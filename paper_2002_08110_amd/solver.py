@@ -113,6 +113,12 @@ class Solver:
                                     _stream(stream)))
         return out
 
+    def set_quadrature(self, quadrature="gauss_lobatto"):
+        """'gauss_lobatto' (collocation, the default) or 'gauss_legendre'
+        (k+1 Gauss points per dimension)."""
+        q = {"gauss_lobatto": 0, "gauss_legendre": 1}[quadrature]
+        check(self.lib.hd_set_quadrature(self.h, q))
+
     def compute_field(self, stream=None):
         """Recompute the device E table of the Vlasov-Poisson field from the
         current state (asynchronous; no-op for prescribed fields)."""
