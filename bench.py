@@ -43,12 +43,16 @@ def parse():
     ap.add_argument("--precisions", default="fp64,fp32")
     ap.add_argument("--plan", default="", help="override plan, e.g. lds=1,reg_dims=1")
     ap.add_argument("--mode", default="bench",
-                    choices=["bench", "stages", "copy", "batch", "serve", "vp"],
+                    choices=["bench", "stages", "copy", "batch", "serve", "vp", "gauss"],
                     help="stages: only run --steps x 5 stage launches per precision (for "
                          "profilers); copy: a plain device copy of --copy-mib MiB (the "
                          "calibration kernel for the byte counters); batch: the 96-solve "
                          "mix; serve: a prefix of the seeded request trace; vp: the 6D "
-                         "Vlasov-Poisson stage (self-consistent field each stage)")
+                         "Vlasov-Poisson stage (self-consistent field each stage); gauss: "
+                         "the workload with Gauss-Legendre quadrature beside collocation")
+    ap.add_argument("--quadrature", default="gauss_lobatto",
+                    choices=["gauss_lobatto", "gauss_legendre"],
+                    help="stages: quadrature of the profiled run")
     ap.add_argument("--modes", type=int, default=4, help="vp: Fourier modes per x-dimension")
     ap.add_argument("--copy-mib", type=int, default=4096)
     ap.add_argument("--requests", type=int, default=24, help="serve: trace prefix length")
@@ -61,7 +65,7 @@ def parse():
     return ap.parse_args()
 
 
-def run_stages(case, precision, steps, plan_override):
+def run_stages(case, precision, steps, plan_override, quadrature="gauss_lobatto"):
     """Only the fused stage launches (5 per step), for counter collection."""
     import torch
 
@@ -74,6 +78,8 @@ def run_stages(case, precision, steps, plan_override):
         S.set_field_constant(case.a)
     if plan_override:
         S.set_plan(**plan_override)
+    if quadrature != "gauss_lobatto":
+        S.set_quadrature(quadrature)
     S.init_state(case.ic, list(case.ic_params))
     dt = S.stable_dt(case.cfl)
     for _ in range(steps):
@@ -112,7 +118,7 @@ def run_copy(mib):
           % (mib, ms, 2 * n * 8 / ms / 1e6), file=sys.stderr, flush=True)
 
 
-def measure(case, precision, steps, warmup, plan_override):
+def measure(case, precision, steps, warmup, plan_override, quadrature="gauss_lobatto"):
     import torch
 
     from paper_2002_08110_amd.solver import Solver
@@ -124,6 +130,8 @@ def measure(case, precision, steps, warmup, plan_override):
         S.set_field_constant(case.a)
     if plan_override:
         S.set_plan(**plan_override)
+    if quadrature != "gauss_lobatto":
+        S.set_quadrature(quadrature)
     S.init_state(case.ic, list(case.ic_params))
     dt = S.stable_dt(case.cfl)
     stream = torch.cuda.current_stream()
@@ -163,7 +171,8 @@ def measure(case, precision, steps, warmup, plan_override):
         dof_updates_per_s=S.ndofs * 5 / (ms_step * 1e-3),
         stage_ms=[round(float(x), 4) for x in stage_ms],
         stage_kernel_GBps=achieved, algorithmic_bytes_per_dof=float(np.mean(stage_bytes(psize))),
-        plan=S.get_plan(), mass_drift=(m1 - m0) / abs(m0), energy_ratio=e1 / e0,
+        plan=S.get_plan() if quadrature == "gauss_lobatto" else "stage_gauss_kernel",
+        quadrature=quadrature, mass_drift=(m1 - m0) / abs(m0), energy_ratio=e1 / e0,
     )
     S.close()
     del S
@@ -348,6 +357,36 @@ def run_vp(steps, warmup, precisions, modes):
     print(json.dumps(out), flush=True)
 
 
+def run_gauss(case, steps, warmup, precisions):
+    """The workload with Gauss-Legendre quadrature (k+1 Gauss points per
+    dimension: basis change to the points and back, the exact mass matrix)
+    and, in the same run, with collocation. Prints one JSON line."""
+    out = {"metric": "6D k=3 DoF-updates/s per RK stage, Gauss-Legendre quadrature",
+           "unit": "DoF-updates/s", "workload": case.name, "modes": {},
+           "paper_context": "on average 15% slower than collocation on CPUs while the "
+                            "interpolated data stays in cache (Fig. performance:alternatives c)"}
+    for prec in precisions:
+        g = measure(case, prec, steps, warmup, {}, quadrature="gauss_legendre")
+        c = measure(case, prec, steps, warmup, {})
+        out["modes"][prec] = {
+            "gauss_dof_updates_per_s": g["dof_updates_per_s"], "gauss_stage_ms": g["stage_ms"],
+            "gauss_stage_kernel_GBps": g["stage_kernel_GBps"],
+            "collocation_dof_updates_per_s": c["dof_updates_per_s"],
+            "gauss_over_collocation_time": c["dof_updates_per_s"] / g["dof_updates_per_s"],
+            "mass_drift": g["mass_drift"]}
+        print("# %s: Gauss %.1f GDoF/s (%.0f GB/s), collocation %.1f GDoF/s, time ratio %.2f"
+              % (prec, g["dof_updates_per_s"] / 1e9, g["stage_kernel_GBps"],
+                 c["dof_updates_per_s"] / 1e9, out["modes"][prec]["gauss_over_collocation_time"]),
+              file=sys.stderr, flush=True)
+    head = out["modes"].get("fp64") or next(iter(out["modes"].values()))
+    out["value"] = head["gauss_dof_updates_per_s"]
+    gb = head["gauss_stage_kernel_GBps"]
+    out["roofline"] = {"bound": "hbm", "kernel": "stage_gauss_kernel<6,4,3,double>",
+                       "achieved": gb, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                       "frac": gb / HBM_PEAK_GBPS, "algorithmic_bytes_per_dof": 28.8}
+    print(json.dumps(out), flush=True)
+
+
 def profiled_kernel(precision, plan_override):
     """The committed counter profile of the default plan's stage kernel
     (bytes per launch, VALU activity), or None if the kernel source changed
@@ -427,9 +466,12 @@ def main():
     if args.mode == "vp":
         run_vp(args.steps, args.warmup, args.precisions.split(","), args.modes)
         return
+    if args.mode == "gauss":
+        run_gauss(case, args.steps, args.warmup, args.precisions.split(","))
+        return
     if args.mode == "stages":
         for prec in args.precisions.split(","):
-            run_stages(case, prec, args.steps, plan)
+            run_stages(case, prec, args.steps, plan, args.quadrature)
         return
     results = {}
     for prec in args.precisions.split(","):

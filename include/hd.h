@@ -179,10 +179,9 @@ hd_status hd_get_field(hd_solver *s, double *E_host, hd_stream stream);
  * exactly integrated mass matrix, applied through the basis change to the
  * Gauss points and back; a_v = E enters through the nodal interpolant of
  * the E table). The nodal GL basis and the state layout are the same for
- * both. Quadrature 1 runs one cell per workgroup with the cell and two face
- * layers in LDS and returns HD_ERR_UNSUPPORTED where those exceed 160 KiB
- * (FP64 6D degree >= 4, FP32 6D degree 5; FP64 5D degree 5 is not
- * compiled either). Launch plans apply to
+ * both. Quadrature 1 runs one cell per workgroup with two cell-sized arrays
+ * and a face layer in LDS and returns HD_ERR_UNSUPPORTED where those exceed
+ * 160 KiB (FP64 6D degree >= 4, FP32 6D degree 5). Launch plans apply to
  * quadrature 0 only. */
 hd_status hd_set_quadrature(hd_solver *s, int quadrature);
 

@@ -697,7 +697,8 @@ hd_status hd_set_quadrature(hd_solver *s, int quadrature) {
     if (!s->gtab_ok) return fail(HD_ERR_INVALID, "Gauss-Legendre table construction failed");
     if (!hd::stage_gauss_entry(s->d, s->n, s->prec == HD_FP32))
       return fail(HD_ERR_UNSUPPORTED,
-                  "the Gauss-Legendre kernel holds a cell and two face layers in LDS: this "
+                  "the Gauss-Legendre kernel holds two cell-sized arrays and a face layer in "
+                  "LDS: this "
                   "(d, degree, precision) exceeds 160 KiB");
   }
   s->quad = quadrature;

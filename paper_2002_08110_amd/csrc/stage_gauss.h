@@ -16,7 +16,9 @@
 // layer carried to them by d-1 tangential sweeps, and lift_s = B^{-T} e_s /
 // omega. With GL points (B = I) this is the collocation operator.
 //
-// One workgroup per cell; the cell is transformed in place in LDS.
+// One workgroup per cell; everything is a sweep over lines in LDS: the
+// cell's values at the Gauss points, the operator accumulated beside them,
+// one face layer at a time.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,15 +37,21 @@ struct GaussTables {
   P g[kMaxN];
 };
 
+// Up to 1024 threads: few nodes per thread keep the per-node registers (the
+// accumulated stage operator, u and du) small.
 constexpr int gauss_threads(int nd) { return nd >= 256 ? 256 : (nd + 63) / 64 * 64; }
 
-// LDS elements of P: the cell, two face layers, E at the x-Gauss points.
+// Elements of the 1D tables (B, B^{-1}, Dg, ext, lift, g).
+constexpr int gauss_table_elems(int n) { return 3 * n * n + 5 * n; }
+
+// LDS elements of P: U and the accumulator Y (n^d each), one face layer,
+// E at the x-Gauss points and the 1D tables.
 constexpr int gauss_lds_elems(int d, int n, int dx) {
-  return ipow(n, d) + 2 * ipow(n, d - 1) + ipow(n, dx) * dx;
+  return 2 * ipow(n, d) + ipow(n, d - 1) + ipow(n, dx) * dx + gauss_table_elems(n);
 }
 
-// In place along one axis (stride = N^axis) of consecutive N-ary arrays of
-// `total` elements: every line v <- M v.
+// In place along one axis (stride = N^axis) of an N-ary array of `total`
+// elements: every line v <- M v.
 template <int N, typename P>
 __device__ __forceinline__ void gauss_sweep(P *buf, int total, int stride, const P *M, int t,
                                             int T) {
@@ -67,16 +75,35 @@ __device__ __forceinline__ void gauss_sweep(P *buf, int total, int stride, const
 template <int D, int N, int DX, typename P>
 __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
     stage_gauss_kernel(const StageParams<P> prm, const GaussTables<P> gt) {
-  constexpr int ND = ipow(N, D), NF = ND / N, T = gauss_threads(ND), R = (ND + T - 1) / T;
+  constexpr int ND = ipow(N, D), NF = ND / N, T = gauss_threads(ND);
   constexpr int NXN = ipow(N, DX);
-  // With at most 16 nodes per thread the input solution and du stay in
-  // registers from the start; larger cells read them again for the update.
-  constexpr bool KEEP = R <= 16;
   extern __shared__ unsigned char smem_raw[];
-  P *W = reinterpret_cast<P *>(smem_raw);  // the cell, then U, then Y and L(u)
-  P *F = W + ND;                           // face layers [side][p]
-  P *EG = F + 2 * NF;                      // E at the x-Gauss points [xq][comp]
+  P *W = reinterpret_cast<P *>(smem_raw);  // the cell, then U
+  P *Yb = W + ND;                          // the operator at the Gauss points, then L(u)
+  P *F = Yb + ND;                          // one face layer
+  P *EG = F + NF;                          // E at the x-Gauss points [xq][comp]
+  // 1D tables in LDS, to be indexed per lane. One thread copies them with
+  // compile-time indices: a kernel argument indexed per lane would be copied
+  // whole to scratch.
+  P *tB = EG + NXN * DX, *tBinv = tB + N * N, *tDg = tBinv + N * N;
+  P *tExt = tDg + N * N, *tLift = tExt + 2 * N, *tG = tLift + 2 * N;
   const int t = threadIdx.x;
+  if (t == 0) {
+#pragma unroll
+    for (int i = 0; i < N * N; ++i) {
+      tB[i] = gt.B[i];
+      tBinv[i] = gt.Binv[i];
+      tDg[i] = gt.Dg[i];
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      tExt[i] = gt.ext[0][i];
+      tExt[N + i] = gt.ext[1][i];
+      tLift[i] = gt.lift[0][i];
+      tLift[N + i] = gt.lift[1][i];
+      tG[i] = gt.g[i];
+    }
+  }
   unsigned cell = blockIdx.x;
   if (prm.xcd_remap) cell = xcd_tile(cell, prm.nblocks);
 
@@ -90,33 +117,9 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
   }
   const bool phase = prm.field_kind == 1;
   const bool stage = prm.mode == 1;
-
   const double *ucell = prm.u_in + (uint64_t)cell * ND;
-  P *ducell = prm.du + (uint64_t)cell * ND;
-  constexpr int RK = KEEP ? R : 1;
-  double ud[RK];
-  P dv[RK];
-  if constexpr (KEEP) {
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int q = t + T * r;
-      ud[r] = q < ND ? ucell[q] : 0.0;
-    }
-    if (stage && prm.read_du) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int q = t + T * r;
-        dv[r] = q < ND ? ducell[q] : P(0);
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int q = t + T * r;
-      if (q < ND) W[q] = (P)ud[r];
-    }
-  } else {
-    for (int q = t; q < ND; q += T) W[q] = (P)ucell[q];
-  }
+  for (int q = t; q < ND; q += T) W[q] = (P)ucell[q];
+  __syncthreads();  // tables ready
   if (phase) {
     // E at the x-Gauss points: the nodal interpolant of the cell's E table
     unsigned xcell = 0, xs = 1;
@@ -134,7 +137,7 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
         int a = xq, b = xn;
 #pragma unroll
         for (int m = 0; m < DX; ++m) {
-          ph *= gt.B[(a % N) * N + (b % N)];
+          ph *= tB[(a % N) * N + (b % N)];
           a /= N;
           b /= N;
         }
@@ -143,142 +146,106 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
       EG[idx] = prm.esign * s;
     }
   }
-  __syncthreads();
   // U = (B x ... x B) u
 #pragma unroll
   for (int j = 0; j < D; ++j) {
-    gauss_sweep<N>(W, ND, ipow(N, j), gt.B, t, T);
+    gauss_sweep<N>(W, ND, ipow(N, j), tB, t, T);
     __syncthreads();
   }
 
-  // a_j at a Gauss point given by its digits (digit j itself is not used:
-  // a_j does not depend on x_j).
-  auto a_at = [&](int j, const int *dig) -> P {
+  // a_j at the point with index q (its digit j is not used: a_j does not
+  // depend on x_j)
+  auto a_at = [&](int j, int q) -> P {
     if (!phase) return prm.a_const[j];
-    if (j < DX)
-      return prm.vlo[DX + j] + (P(c[DX + j]) + gt.g[dig[DX + j]]) * prm.vh[DX + j];
-    int xq = 0;
-#pragma unroll
-    for (int m = DX - 1; m >= 0; --m) xq = xq * N + dig[m];
-    return EG[xq * DX + (j - DX)];
+    if (j < DX) {
+      const int dv = (q / ipow(N, DX + j)) % N;
+      return prm.vlo[DX + j] + (P(c[DX + j]) + tG[dv]) * prm.vh[DX + j];
+    }
+    return EG[(q % NXN) * DX + (j - DX)];
   };
 
-  // volume: Y = - sum_j a_j / h_j Dg_j U
-  P Y[R];
+  // volume: Y = - sum_j a_j / h_j Dg_j U, one dimension per sweep
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int q = t + T * r;
-    Y[r] = P(0);
-    if (q >= ND) continue;
-    int dig[D];
-    int rem = q;
-#pragma unroll
-    for (int m = 0; m < D; ++m) {
-      dig[m] = rem % N;
-      rem /= N;
-    }
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-      const int stride = ipow(N, j);
-      const int base = q - dig[j] * stride;
-      P s = P(0);
-#pragma unroll
-      for (int m = 0; m < N; ++m) s += gt.Dg[dig[j] * N + m] * W[base + m * stride];
-      Y[r] -= a_at(j, dig) * prm.inv_h[j] * s;
-    }
-  }
-
-  // faces, one dimension at a time
-#pragma unroll 1
   for (int j = 0; j < D; ++j) {
     const int sj = ipow(N, j);
-    __syncthreads();  // F is free
-    const double *ul = prm.u_in + (uint64_t)left[j] * ND;
-    const double *ur = prm.u_in + (uint64_t)right[j] * ND;
-    for (int idx = t; idx < 2 * NF; idx += T) {
-      const int side = idx / NF, p = idx % NF;
-      const int lo = p % sj, hi = p / sj;
+    const P ih = prm.inv_h[j];
+    for (int l = t; l < NF; l += T) {
+      const int lo = l % sj, hi = l / sj;
+      const int base = lo + hi * sj * N;
+      P v[N];
+#pragma unroll
+      for (int m = 0; m < N; ++m) v[m] = W[base + m * sj];
+      const P coef = -a_at(j, base) * ih;
+#pragma unroll
+      for (int qq = 0; qq < N; ++qq) {
+        P s = tDg[qq * N] * v[0];
+#pragma unroll
+        for (int m = 1; m < N; ++m) s += tDg[qq * N + m] * v[m];
+        if (j == 0) Yb[base + qq * sj] = coef * s;
+        else Yb[base + qq * sj] += coef * s;
+      }
+    }
+    __syncthreads();
+  }
+
+  // faces: per dimension and side, the neighbour's nodal layer carried to
+  // the face Gauss points, the scaled upwind jump, lifted into Y
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    const int sj = ipow(N, j);
+    const P ih = prm.inv_h[j];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
       // side 0 (face xi_j = 0): the left neighbour's layer i_j = k;
       // side 1 (xi_j = 1): the right neighbour's layer i_j = 0
-      const int node = lo + (side ? 0 : N - 1) * sj + hi * sj * N;
-      F[idx] = (P)(side ? ur : ul)[node];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int a = 0; a < D - 1; ++a) {
-      gauss_sweep<N>(F, 2 * NF, ipow(N, a), gt.B, t, T);
-      __syncthreads();
-    }
-    // scaled jumps at the face Gauss points
-    for (int idx = t; idx < 2 * NF; idx += T) {
-      const int side = idx / NF, p = idx % NF;
-      const int lo = p % sj, hi = p / sj;
-      const int base = lo + hi * sj * N;
-      int dig[D];
-      int rem = base;
-#pragma unroll
-      for (int m = 0; m < D; ++m) {
-        dig[m] = rem % N;
-        rem /= N;
+      const double *un = prm.u_in + (uint64_t)(side ? right[j] : left[j]) * ND;
+      for (int p = t; p < NF; p += T) {
+        const int node = p % sj + (side ? 0 : N - 1) * sj + (p / sj) * sj * N;
+        F[p] = (P)un[node];
       }
-      P uo = P(0);
+      __syncthreads();
 #pragma unroll
-      for (int m = 0; m < N; ++m) uo += gt.ext[side][m] * W[base + m * sj];
-      const P a = a_at(j, dig);
-      const P an = side ? a : -a;
-      F[idx] = (an < P(0) ? an : P(0)) * (uo - F[idx]);
-    }
-    __syncthreads();
+      for (int a = 0; a < D - 1; ++a) {
+        gauss_sweep<N>(F, NF, ipow(N, a), tB, t, T);
+        __syncthreads();
+      }
+      for (int p = t; p < NF; p += T) {
+        const int base = p % sj + (p / sj) * sj * N;
+        P uo = P(0);
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int q = t + T * r;
-      if (q >= ND) continue;
-      const int qj = (q / sj) % N;
-      const int p = q % sj + (q / (sj * N)) * sj;
-      Y[r] += prm.inv_h[j] * (gt.lift[0][qj] * F[p] + gt.lift[1][qj] * F[NF + p]);
+        for (int m = 0; m < N; ++m) uo += tExt[side * N + m] * W[base + m * sj];
+        const P a = a_at(j, base);
+        const P an = side ? a : -a;
+        F[p] = (an < P(0) ? an : P(0)) * (uo - F[p]);
+      }
+      __syncthreads();
+      for (int q = t; q < ND; q += T) {
+        const int qj = (q / sj) % N;
+        const int p = q % sj + (q / (sj * N)) * sj;
+        Yb[q] += ih * tLift[side * N + qj] * F[p];
+      }
+      __syncthreads();  // F is free again
     }
   }
-  __syncthreads();  // every read of U is done
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int q = t + T * r;
-    if (q < ND) W[q] = Y[r];
-  }
-  __syncthreads();
   // L(u) = (B^{-1} x ... x B^{-1}) Y
 #pragma unroll
   for (int j = 0; j < D; ++j) {
-    gauss_sweep<N>(W, ND, ipow(N, j), gt.Binv, t, T);
+    gauss_sweep<N>(Yb, ND, ipow(N, j), tBinv, t, T);
     __syncthreads();
   }
 
   if (!stage) {
     P *ocell = prm.out + (uint64_t)cell * ND;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int q = t + T * r;
-      if (q < ND) ocell[q] = W[q];
-    }
+    for (int q = t; q < ND; q += T) ocell[q] = Yb[q];
     return;
   }
+  P *ducell = prm.du + (uint64_t)cell * ND;
   double *uocell = prm.u_out + (uint64_t)cell * ND;
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int q = t + T * r;
-    if (q >= ND) continue;
-    const P L = W[q];
-    P dold;
-    double uin;
-    if constexpr (KEEP) {
-      dold = dv[r];
-      uin = ud[r];
-    } else {
-      dold = prm.read_du ? ducell[q] : P(0);
-      uin = ucell[q];
-    }
-    const P dn = prm.read_du ? prm.rk_a * dold + prm.dt * L : prm.dt * L;
+  for (int q = t; q < ND; q += T) {
+    const P L = Yb[q];
+    const P dn = prm.read_du ? prm.rk_a * ducell[q] + prm.dt * L : prm.dt * L;
     if (prm.write_du) ducell[q] = dn;
-    uocell[q] = uin + prm.rk_b * (double)dn;
+    uocell[q] = ucell[q] + prm.rk_b * (double)dn;
   }
 }
 

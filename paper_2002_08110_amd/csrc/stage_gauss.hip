@@ -1,18 +1,16 @@
 // Entries of the Gauss-Legendre stage kernel: d = 2..6 (x/v split as for the
 // collocation kernels), degree 1..5, FP64 and FP32; only variants whose LDS
-// (the cell, two face layers, E at the x-Gauss points) fits 160 KiB exist.
+// (U and the accumulated operator, one face layer, E at the x-Gauss points,
+// the 1D tables) fits 160 KiB exist.
 #include "stage_dispatch.h"
 #include "stage_gauss.h"
 
 namespace hd {
 namespace {
 
-// 5D degree 5 in FP64 (31 nodes per thread) is left out: hipcc for gfx950
-// rejects that instantiation with an instruction-selection error.
 template <int D, int N, int DX, typename P>
 constexpr bool gauss_compiled() {
-  return (size_t)gauss_lds_elems(D, N, DX) * sizeof(P) <= kMaxLdsBytes &&
-         !(D == 5 && N == 6 && sizeof(P) == 8);
+  return (size_t)gauss_lds_elems(D, N, DX) * sizeof(P) <= kMaxLdsBytes;
 }
 
 template <int D, int N, int DX, typename P>
