@@ -251,8 +251,13 @@ hipError_t allow_large_lds(const void *fn) {
   static std::unordered_set<const void *> done;
   std::lock_guard<std::mutex> lock(mu);
   if (done.count(fn)) return hipSuccess;
-  hipError_t e =
-      hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)hd::kMaxLdsBytes);
+  // The dynamic limit is what the workgroup maximum leaves beside the
+  // kernel's static LDS (e.g. a workgroup reduction's).
+  hipFuncAttributes fa{};
+  hipError_t e = hipFuncGetAttributes(&fa, fn);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)(hd::kMaxLdsBytes - fa.sharedSizeBytes));
   if (e == hipSuccess) done.insert(fn);
   return e;
 }

@@ -196,6 +196,14 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
     const P ih = prm.inv_h[j];
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
+      // A side none of whose Gauss points is inflow contributes nothing (one
+      // side per dimension where a_j keeps its sign over the face).
+      int inflow = 0;
+      for (int p = t; p < NF; p += T) {
+        const P a = a_at(j, p % sj + (p / sj) * sj * N);
+        inflow |= side ? (a < P(0)) : (a > P(0));
+      }
+      if (!__syncthreads_or(inflow)) continue;
       // side 0 (face xi_j = 0): the left neighbour's layer i_j = k;
       // side 1 (xi_j = 1): the right neighbour's layer i_j = 0
       const double *un = prm.u_in + (uint64_t)(side ? right[j] : left[j]) * ND;

@@ -8,9 +8,11 @@
 namespace hd {
 namespace {
 
+// 1 KiB is kept free for the kernel's static LDS (the workgroup reduction
+// behind __syncthreads_or).
 template <int D, int N, int DX, typename P>
 constexpr bool gauss_compiled() {
-  return (size_t)gauss_lds_elems(D, N, DX) * sizeof(P) <= kMaxLdsBytes;
+  return (size_t)gauss_lds_elems(D, N, DX) * sizeof(P) + 1024 <= kMaxLdsBytes;
 }
 
 template <int D, int N, int DX, typename P>

@@ -40,7 +40,7 @@ def supported(d, k, precision):
     dx = W.SPLITS[d][0]
     lds = (2 * n ** d + n ** (d - 1) + n ** dx * dx + 3 * n * n + 5 * n) * (
         8 if precision == "fp64" else 4)
-    return lds <= 160 * 1024
+    return lds + 1024 <= 160 * 1024
 
 
 def _cost_ok(d, k, ncells):
