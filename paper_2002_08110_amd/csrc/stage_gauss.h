@@ -44,10 +44,18 @@ constexpr int gauss_threads(int nd) { return nd >= 256 ? 256 : (nd + 63) / 64 * 
 // Elements of the 1D tables (B, B^{-1}, Dg, ext, lift, g).
 constexpr int gauss_table_elems(int n) { return 3 * n * n + 5 * n; }
 
+// LDS arrays are padded by one element after every n^2: a thread's n x n
+// plane then starts n^2 + 1 elements after its neighbour's, which spreads
+// the lanes of a sweep over the banks.
+template <int N>
+__host__ __device__ constexpr int gauss_pad(int q) { return q + q / (N * N); }
+constexpr int gauss_padded(int n, int count) { return count + count / (n * n) + 1; }
+
 // LDS elements of P: U and the accumulator Y (n^d each), one face layer,
 // E at the x-Gauss points and the 1D tables.
 constexpr int gauss_lds_elems(int d, int n, int dx) {
-  return 2 * ipow(n, d) + ipow(n, d - 1) + ipow(n, dx) * dx + gauss_table_elems(n);
+  return 2 * gauss_padded(n, ipow(n, d)) + gauss_padded(n, ipow(n, d - 1)) + ipow(n, dx) * dx +
+         gauss_table_elems(n);
 }
 
 // In place along one axis (stride = N^axis) of an N-ary array of `total`
@@ -58,17 +66,72 @@ __device__ __forceinline__ void gauss_sweep(P *buf, int total, int stride, const
   const int lines = total / N;
   for (int l = t; l < lines; l += T) {
     const int lo = l % stride, hi = l / stride;
-    P *p = buf + lo + hi * stride * N;
+    const int base = lo + hi * stride * N;
     P v[N];
 #pragma unroll
-    for (int m = 0; m < N; ++m) v[m] = p[m * stride];
+    for (int m = 0; m < N; ++m) v[m] = buf[gauss_pad<N>(base + m * stride)];
 #pragma unroll
     for (int q = 0; q < N; ++q) {
       P s = M[q * N] * v[0];
 #pragma unroll
       for (int m = 1; m < N; ++m) s += M[q * N + m] * v[m];
-      p[q * stride] = s;
+      buf[gauss_pad<N>(base + q * stride)] = s;
     }
+  }
+}
+
+// In place along two adjacent axes (strides st and st * N) of an N-ary
+// array: every N x N plane v <- M v M^T, kept in registers between the two
+// passes (one barrier for two dimensions).
+template <int N, typename P>
+__device__ __forceinline__ void gauss_sweep2(P *buf, int total, int st, const P *M, int t,
+                                             int T) {
+  const int planes = total / (N * N);
+  for (int l = t; l < planes; l += T) {
+    const int lo = l % st, hi = l / st;
+    const int base = lo + hi * st * N * N;
+    P v[N][N];
+#pragma unroll
+    for (int a = 0; a < N; ++a)
+#pragma unroll
+      for (int b = 0; b < N; ++b) v[a][b] = buf[gauss_pad<N>(base + a * st + b * st * N)];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      P w[N];
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        P s = M[q * N] * v[0][b];
+#pragma unroll
+        for (int m = 1; m < N; ++m) s += M[q * N + m] * v[m][b];
+        w[q] = s;
+      }
+#pragma unroll
+      for (int q = 0; q < N; ++q) v[q][b] = w[q];
+    }
+#pragma unroll
+    for (int a = 0; a < N; ++a)
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        P s = M[q * N] * v[a][0];
+#pragma unroll
+        for (int m = 1; m < N; ++m) s += M[q * N + m] * v[a][m];
+        buf[gauss_pad<N>(base + a * st + q * st * N)] = s;
+      }
+  }
+}
+
+// All DIMS axes of an N^DIMS array, two at a time.
+template <int N, int DIMS, typename P>
+__device__ __forceinline__ void gauss_transform(P *buf, const P *M, int t, int T) {
+  constexpr int total = ipow(N, DIMS);
+#pragma unroll
+  for (int a = 0; a + 1 < DIMS; a += 2) {
+    gauss_sweep2<N>(buf, total, ipow(N, a), M, t, T);
+    __syncthreads();
+  }
+  if constexpr (DIMS % 2 == 1) {
+    gauss_sweep<N>(buf, total, ipow(N, DIMS - 1), M, t, T);
+    __syncthreads();
   }
 }
 
@@ -78,10 +141,10 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
   constexpr int ND = ipow(N, D), NF = ND / N, T = gauss_threads(ND);
   constexpr int NXN = ipow(N, DX);
   extern __shared__ unsigned char smem_raw[];
-  P *W = reinterpret_cast<P *>(smem_raw);  // the cell, then U
-  P *Yb = W + ND;                          // the operator at the Gauss points, then L(u)
-  P *F = Yb + ND;                          // one face layer
-  P *EG = F + NF;                          // E at the x-Gauss points [xq][comp]
+  P *W = reinterpret_cast<P *>(smem_raw);      // the cell, then U
+  P *Yb = W + gauss_padded(N, ND);             // the operator at the Gauss points, then L(u)
+  P *F = Yb + gauss_padded(N, ND);             // one face layer
+  P *EG = F + gauss_padded(N, NF);             // E at the x-Gauss points [xq][comp]
   // 1D tables in LDS, to be indexed per lane. One thread copies them with
   // compile-time indices: a kernel argument indexed per lane would be copied
   // whole to scratch.
@@ -118,7 +181,7 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
   const bool phase = prm.field_kind == 1;
   const bool stage = prm.mode == 1;
   const double *ucell = prm.u_in + (uint64_t)cell * ND;
-  for (int q = t; q < ND; q += T) W[q] = (P)ucell[q];
+  for (int q = t; q < ND; q += T) W[gauss_pad<N>(q)] = (P)ucell[q];
   __syncthreads();  // tables ready
   if (phase) {
     // E at the x-Gauss points: the nodal interpolant of the cell's E table
@@ -147,11 +210,7 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
     }
   }
   // U = (B x ... x B) u
-#pragma unroll
-  for (int j = 0; j < D; ++j) {
-    gauss_sweep<N>(W, ND, ipow(N, j), tB, t, T);
-    __syncthreads();
-  }
+  gauss_transform<N, D>(W, tB, t, T);
 
   // a_j at the point with index q (its digit j is not used: a_j does not
   // depend on x_j)
@@ -164,9 +223,39 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
     return EG[(q % NXN) * DX + (j - DX)];
   };
 
-  // volume: Y = - sum_j a_j / h_j Dg_j U, one dimension per sweep
+  // volume: Y = - sum_j a_j / h_j Dg_j U, two dimensions per pass (each
+  // thread owns an N x N plane), the odd one last
 #pragma unroll
-  for (int j = 0; j < D; ++j) {
+  for (int j = 0; j + 1 < D; j += 2) {
+    const int sj = ipow(N, j);
+    const P ih0 = prm.inv_h[j], ih1 = prm.inv_h[j + 1];
+    for (int l = t; l < ND / (N * N); l += T) {
+      const int base = l % sj + (l / sj) * sj * N * N;
+      P v[N][N];
+#pragma unroll
+      for (int a = 0; a < N; ++a)
+#pragma unroll
+        for (int b = 0; b < N; ++b) v[a][b] = W[gauss_pad<N>(base + a * sj + b * sj * N)];
+#pragma unroll
+      for (int a = 0; a < N; ++a)
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+          P d0 = tDg[a * N] * v[0][b], d1 = tDg[b * N] * v[a][0];
+#pragma unroll
+          for (int m = 1; m < N; ++m) {
+            d0 += tDg[a * N + m] * v[m][b];
+            d1 += tDg[b * N + m] * v[a][m];
+          }
+          const int q = base + a * sj + b * sj * N;
+          const P y = -(a_at(j, q) * ih0 * d0 + a_at(j + 1, q) * ih1 * d1);
+          if (j == 0) Yb[gauss_pad<N>(q)] = y;
+          else Yb[gauss_pad<N>(q)] += y;
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = D - (D % 2); j < D; ++j) {
     const int sj = ipow(N, j);
     const P ih = prm.inv_h[j];
     for (int l = t; l < NF; l += T) {
@@ -174,15 +263,15 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
       const int base = lo + hi * sj * N;
       P v[N];
 #pragma unroll
-      for (int m = 0; m < N; ++m) v[m] = W[base + m * sj];
+      for (int m = 0; m < N; ++m) v[m] = W[gauss_pad<N>(base + m * sj)];
       const P coef = -a_at(j, base) * ih;
 #pragma unroll
       for (int qq = 0; qq < N; ++qq) {
         P s = tDg[qq * N] * v[0];
 #pragma unroll
         for (int m = 1; m < N; ++m) s += tDg[qq * N + m] * v[m];
-        if (j == 0) Yb[base + qq * sj] = coef * s;
-        else Yb[base + qq * sj] += coef * s;
+        if (j == 0) Yb[gauss_pad<N>(base + qq * sj)] = coef * s;
+        else Yb[gauss_pad<N>(base + qq * sj)] += coef * s;
       }
     }
     __syncthreads();
@@ -209,48 +298,40 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
       const double *un = prm.u_in + (uint64_t)(side ? right[j] : left[j]) * ND;
       for (int p = t; p < NF; p += T) {
         const int node = p % sj + (side ? 0 : N - 1) * sj + (p / sj) * sj * N;
-        F[p] = (P)un[node];
+        F[gauss_pad<N>(p)] = (P)un[node];
       }
       __syncthreads();
-#pragma unroll
-      for (int a = 0; a < D - 1; ++a) {
-        gauss_sweep<N>(F, NF, ipow(N, a), tB, t, T);
-        __syncthreads();
-      }
+      gauss_transform<N, D - 1>(F, tB, t, T);
       for (int p = t; p < NF; p += T) {
         const int base = p % sj + (p / sj) * sj * N;
         P uo = P(0);
 #pragma unroll
-        for (int m = 0; m < N; ++m) uo += tExt[side * N + m] * W[base + m * sj];
+        for (int m = 0; m < N; ++m) uo += tExt[side * N + m] * W[gauss_pad<N>(base + m * sj)];
         const P a = a_at(j, base);
         const P an = side ? a : -a;
-        F[p] = (an < P(0) ? an : P(0)) * (uo - F[p]);
+        F[gauss_pad<N>(p)] = (an < P(0) ? an : P(0)) * (uo - F[gauss_pad<N>(p)]);
       }
       __syncthreads();
       for (int q = t; q < ND; q += T) {
         const int qj = (q / sj) % N;
         const int p = q % sj + (q / (sj * N)) * sj;
-        Yb[q] += ih * tLift[side * N + qj] * F[p];
+        Yb[gauss_pad<N>(q)] += ih * tLift[side * N + qj] * F[gauss_pad<N>(p)];
       }
       __syncthreads();  // F is free again
     }
   }
   // L(u) = (B^{-1} x ... x B^{-1}) Y
-#pragma unroll
-  for (int j = 0; j < D; ++j) {
-    gauss_sweep<N>(Yb, ND, ipow(N, j), tBinv, t, T);
-    __syncthreads();
-  }
+  gauss_transform<N, D>(Yb, tBinv, t, T);
 
   if (!stage) {
     P *ocell = prm.out + (uint64_t)cell * ND;
-    for (int q = t; q < ND; q += T) ocell[q] = Yb[q];
+    for (int q = t; q < ND; q += T) ocell[q] = Yb[gauss_pad<N>(q)];
     return;
   }
   P *ducell = prm.du + (uint64_t)cell * ND;
   double *uocell = prm.u_out + (uint64_t)cell * ND;
   for (int q = t; q < ND; q += T) {
-    const P L = Yb[q];
+    const P L = Yb[gauss_pad<N>(q)];
     const P dn = prm.read_du ? prm.rk_a * ducell[q] + prm.dt * L : prm.dt * L;
     if (prm.write_du) ducell[q] = dn;
     uocell[q] = ucell[q] + prm.rk_b * (double)dn;

@@ -38,7 +38,9 @@ def case_of(d, k, field):
 def supported(d, k, precision):
     n = k + 1
     dx = W.SPLITS[d][0]
-    lds = (2 * n ** d + n ** (d - 1) + n ** dx * dx + 3 * n * n + 5 * n) * (
+    def padded(c):  # one element of padding per n^2
+        return c + c // (n * n) + 1
+    lds = (2 * padded(n ** d) + padded(n ** (d - 1)) + n ** dx * dx + 3 * n * n + 5 * n) * (
         8 if precision == "fp64" else 4)
     return lds + 1024 <= 160 * 1024
 
