@@ -37,7 +37,7 @@ def build(force: bool = False) -> str:
 class Mesh(ctypes.Structure):
     _fields_ = [("dim_x", ctypes.c_int), ("dim_v", ctypes.c_int),
                 ("cells", ctypes.c_int * 6), ("lo", ctypes.c_double * 6),
-                ("hi", ctypes.c_double * 6)]
+                ("hi", ctypes.c_double * 6), ("map_eps", ctypes.c_double)]
 
 
 class Field(ctypes.Structure):
@@ -88,10 +88,11 @@ def _dp(a: np.ndarray):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def make_mesh(dim_x, dim_v, cells, lo, hi) -> Mesh:
+def make_mesh(dim_x, dim_v, cells, lo, hi, map_eps=0.0) -> Mesh:
     d = dim_x + dim_v
     m = Mesh()
     m.dim_x, m.dim_v = dim_x, dim_v
+    m.map_eps = float(map_eps)
     for j in range(d):
         m.cells[j] = int(cells[j])
         m.lo[j] = float(lo[j])
@@ -103,7 +104,7 @@ class Problem:
     """A mesh, a degree and a field; holds the E table alive for ctypes."""
 
     def __init__(self, dim_x, dim_v, cells, lo, hi, k, field="constant", a=None,
-                 E=None, sign=1.0, sine_amp=None):
+                 E=None, sign=1.0, sine_amp=None, map_eps=0.0):
         self.lib = _load()
         self.dim_x, self.dim_v, self.k = dim_x, dim_v, k
         self.d = dim_x + dim_v
@@ -111,7 +112,8 @@ class Problem:
         self.cells = [int(c) for c in cells]
         self.lo = [float(x) for x in lo]
         self.hi = [float(x) for x in hi]
-        self.mesh = make_mesh(dim_x, dim_v, cells, lo, hi)
+        self.map_eps = float(map_eps)
+        self.mesh = make_mesh(dim_x, dim_v, cells, lo, hi, map_eps)
         self.ndofs = int(self.lib.or_num_dofs(ctypes.byref(self.mesh), k))
         if self.ndofs < 0:
             raise ValueError("invalid mesh/degree")

@@ -148,6 +148,8 @@ typedef struct {
   double LG[OR_MAXN][OR_MAXN];  /* LG[m][q] = l_m(g_q) */
   double DLG[OR_MAXN][OR_MAXN]; /* DLG[m][q] = l_m'(g_q) */
   double MG[OR_MAXN][OR_MAXN], MGinv[OR_MAXN][OR_MAXN];
+  double Binv[OR_MAXN][OR_MAXN]; /* inverse of B[q][i] = l_i(g_q) */
+  double eps;                    /* x-space deformation (0: Cartesian) */
 } or_geom;
 
 /* Inverse of the n x n matrix A by Gauss-Jordan elimination with partial
@@ -235,7 +237,41 @@ static int setup_geom(const or_mesh *mesh, int k, or_geom *g) {
       g->MG[a][b] = m;
     }
   if (invert(g->n, g->MG, g->MGinv)) return -1;
+  {
+    double Bm[OR_MAXN][OR_MAXN];
+    for (int q = 0; q <= k; ++q)
+      for (int i = 0; i <= k; ++i) Bm[q][i] = g->LG[i][q];
+    if (invert(g->n, Bm, g->Binv)) return -1;
+  }
+  g->eps = mesh->map_eps;
+  if (!(fabs(g->eps) <= 0.05)) return -1;
   return 0;
+}
+
+/* The mapping of the box point X (d coordinates; only the first dx change):
+ * x_m = X_m + eps L_m prod_k sin(theta_k), theta_k = 2 pi (X_k - lo_k)/L_k,
+ * and its derivative Jx[m][k] = dx_m / dX_k for m, k < dx. */
+static void map_point(const or_geom *g, const double *X, double *x, double Jx[3][3]) {
+  double s[3], c[3];
+  for (int k = 0; k < g->dx; ++k) {
+    const double L = g->hi[k] - g->lo[k];
+    const double th = 2.0 * OR_PI * (X[k] - g->lo[k]) / L;
+    s[k] = sin(th);
+    c[k] = cos(th);
+  }
+  for (int m = 0; m < g->d; ++m) x[m] = X[m];
+  double prod = 1.0;
+  for (int k = 0; k < g->dx; ++k) prod *= s[k];
+  for (int m = 0; m < g->dx; ++m) {
+    const double Lm = g->hi[m] - g->lo[m];
+    x[m] += g->eps * Lm * prod;
+    for (int k = 0; k < g->dx; ++k) {
+      double p = 1.0;
+      for (int r = 0; r < g->dx; ++r) p *= (r == k) ? c[r] : s[r];
+      const double Lk = g->hi[k] - g->lo[k];
+      Jx[m][k] = (m == k ? 1.0 : 0.0) + g->eps * Lm * (2.0 * OR_PI / Lk) * p;
+    }
+  }
 }
 
 static void cell_multi(const or_geom *g, int64_t c, int *cm) {
@@ -263,9 +299,14 @@ static int64_t neighbour_cell(const or_geom *g, const int *cm, int j, int dir) {
   return cell_linear(g, nm);
 }
 
-/* Physical coordinate of node qm of cell cm in dim j. */
+/* Physical coordinate of node qm of cell cm in dim j (through the mapping
+ * for the configuration dims). */
 static double node_coord(const or_geom *g, const int *cm, const int *qm, int j) {
-  return g->lo[j] + (cm[j] + g->xi[qm[j]]) * g->h[j];
+  if (g->eps == 0.0 || j >= g->dx) return g->lo[j] + (cm[j] + g->xi[qm[j]]) * g->h[j];
+  double X[OR_MAXD], x[OR_MAXD], Jx[3][3];
+  for (int m = 0; m < g->d; ++m) X[m] = g->lo[m] + (cm[m] + g->xi[qm[m]]) * g->h[m];
+  map_point(g, X, x, Jx);
+  return x[j];
 }
 
 /* Advection field component j at node qm of cell cm (Sec. 6.1: v from the
@@ -617,12 +658,203 @@ static void eval_cell_gauss(const or_geom *g, const or_field *f, const double *u
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* The weak form with the metric terms (mapped cells; Sec. 2.5, 3.3)          */
+/* ------------------------------------------------------------------------ */
+
+/* Reference point xi (d coordinates in [0,1]) of cell cm: the box point X,
+ * the physical point x, |J| and the contravariant field |J| J^{-1} a, with
+ * J = d x / d xi block diagonal (the mapped x-block times h, diag(h) for v). */
+static void metric_at(const or_geom *g, const or_field *f, const int *cm, const double *xi,
+                      const int *qm, int gauss, double *detJ, double *ahat) {
+  const int d = g->d, dx = g->dx;
+  double X[OR_MAXD], x[OR_MAXD], Jx[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  for (int m = 0; m < d; ++m) X[m] = g->lo[m] + (cm[m] + xi[m]) * g->h[m];
+  map_point(g, X, x, Jx);
+  /* x-block of J: Jx diag(h_x); its determinant and |J_x| J_x^{-1} by
+   * cofactors (adjugate). */
+  double A[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  for (int m = 0; m < dx; ++m)
+    for (int kk = 0; kk < dx; ++kk) A[m][kk] = Jx[m][kk] * g->h[kk];
+  double detx, adj[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  if (dx == 1) {
+    detx = A[0][0];
+    adj[0][0] = 1.0;
+  } else if (dx == 2) {
+    detx = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+    adj[0][0] = A[1][1];
+    adj[0][1] = -A[0][1];
+    adj[1][0] = -A[1][0];
+    adj[1][1] = A[0][0];
+  } else {
+    detx = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+           A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+           A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+    for (int r = 0; r < 3; ++r)
+      for (int cc = 0; cc < 3; ++cc) {
+        /* adj[r][cc] = cofactor of A[cc][r] */
+        const int r1 = (cc + 1) % 3, r2 = (cc + 2) % 3, c1 = (r + 1) % 3, c2 = (r + 2) % 3;
+        adj[r][cc] = A[r1][c1] * A[r2][c2] - A[r1][c2] * A[r2][c1];
+      }
+  }
+  double detv = 1.0;
+  for (int m = dx; m < d; ++m) detv *= g->h[m];
+  *detJ = detx * detv;
+  /* physical field at the point */
+  double a[OR_MAXD];
+  for (int j = 0; j < d; ++j)
+    a[j] = gauss ? field_at_gauss(g, f, cm, qm, j) : field_at(g, f, cm, qm, j);
+  /* |J| J^{-1} a: x-block detv * adj(A) a_x, v-block detx * detv / h a_v */
+  for (int j = 0; j < dx; ++j) {
+    double s = 0.0;
+    for (int kk = 0; kk < dx; ++kk) s += adj[j][kk] * a[kk];
+    ahat[j] = detv * s;
+  }
+  for (int j = dx; j < d; ++j) ahat[j] = detx * detv / g->h[j] * a[j];
+}
+
+/* The weak form of Sec. 1.3 on a mapped cell with quadrature at the GL
+ * points (gauss = 0: nodal, diagonal mass W |J|) or the Gauss points
+ * (gauss = 1: mass B^T diag(W |J|) B per cell, B[q][i] = l_i(g_q) square,
+ * inverted as B^{-1} diag(W |J|)^{-1} B^{-T}):
+ *   V_i = sum_q W_q sum_j d/dxi_j phi_i(q) ahat_j(q) u_h(q),
+ *   F_i = sum_faces sum_p W^f_p phi_i(p) (ahat_j n_j)(p) u*(p), upwind u*,
+ * with reference weights W and the reference normal n_j = -1 / +1. */
+static void eval_cell_general(const or_geom *g, const or_field *f, int gauss,
+                              const double *u, int64_t c, double *out, or_scratch *s) {
+  const int d = g->d, k = g->k;
+  const int64_t nd = g->nd;
+  const double *pt = gauss ? g->gq : g->xi;
+  const double *wt = gauss ? g->wg : g->w;
+  int cm[OR_MAXD], im[OR_MAXD], qm[OR_MAXD];
+  cell_multi(g, c, cm);
+  const double *uc = u + c * nd;
+  for (int64_t q = 0; q < nd; ++q) node_multi(g, q, s->multi + q * d);
+  /* L1[m][q] = l_m(pt_q), D1[m][q] = l_m'(pt_q) */
+  double L1[OR_MAXN][OR_MAXN], D1[OR_MAXN][OR_MAXN];
+  for (int m = 0; m <= k; ++m)
+    for (int q = 0; q <= k; ++q) {
+      L1[m][q] = gauss ? g->LG[m][q] : g->L[m][q];
+      D1[m][q] = gauss ? g->DLG[m][q] : g->DL[m][q];
+    }
+  /* u_h, |J| and ahat at the cell's quadrature points; acell holds ahat,
+   * rhs temporarily nothing */
+  double *detJ = (double *)malloc(sizeof(double) * nd);
+  for (int64_t q = 0; q < nd; ++q) {
+    memcpy(qm, s->multi + q * d, sizeof(int) * d);
+    double xi[OR_MAXD];
+    for (int m = 0; m < d; ++m) xi[m] = pt[qm[m]];
+    metric_at(g, f, cm, xi, qm, gauss, &detJ[q], s->acell + q * d);
+    double v = 0.0;
+    for (int64_t ip = 0; ip < nd; ++ip) {
+      memcpy(im, s->multi + ip * d, sizeof(int) * d);
+      double ph = 1.0;
+      for (int m = 0; m < d; ++m) ph *= L1[im[m]][qm[m]];
+      v += uc[ip] * ph;
+    }
+    s->uh[q] = v;
+  }
+  for (int64_t i = 0; i < nd; ++i) {
+    memcpy(im, s->multi + i * d, sizeof(int) * d);
+    double v = 0.0;
+    for (int64_t q = 0; q < nd; ++q) {
+      memcpy(qm, s->multi + q * d, sizeof(int) * d);
+      double W = 1.0;
+      for (int m = 0; m < d; ++m) W *= wt[qm[m]];
+      for (int j = 0; j < d; ++j) {
+        double dphi = D1[im[j]][qm[j]];
+        for (int m = 0; m < d; ++m)
+          if (m != j) dphi *= L1[im[m]][qm[m]];
+        v += W * dphi * s->acell[q * d + j] * s->uh[q];
+      }
+    }
+    s->rhs[i] = v;
+  }
+  for (int j = 0; j < d; ++j)
+    for (int side = 0; side < 2; ++side) {
+      const int pj = side ? k : 0, oj = side ? 0 : k;
+      const double nj = side ? 1.0 : -1.0;
+      const int64_t cn = neighbour_cell(g, cm, j, side ? +1 : -1);
+      const double *un = u + cn * nd;
+      for (int64_t p = 0; p < nd; ++p) {
+        memcpy(qm, s->multi + p * d, sizeof(int) * d);
+        if (qm[j] != 0) continue; /* one pass over the tangential points */
+        double xi[OR_MAXD];
+        for (int m = 0; m < d; ++m) xi[m] = pt[qm[m]];
+        xi[j] = side ? 1.0 : 0.0;
+        double dJ, ah[OR_MAXD];
+        metric_at(g, f, cm, xi, qm, gauss, &dJ, ah);
+        double uown = 0.0, unbr = 0.0;
+        for (int64_t ip = 0; ip < nd; ++ip) {
+          memcpy(im, s->multi + ip * d, sizeof(int) * d);
+          if (im[j] != pj && im[j] != oj) continue;
+          double ph = 1.0;
+          for (int m = 0; m < d; ++m)
+            if (m != j) ph *= L1[im[m]][qm[m]];
+          if (im[j] == pj) uown += uc[ip] * ph;
+          if (im[j] == oj) unbr += un[ip] * ph;
+        }
+        const double an = ah[j] * nj;
+        const double ustar = an >= 0.0 ? uown : unbr;
+        double Wf = 1.0;
+        for (int m = 0; m < d; ++m)
+          if (m != j) Wf *= wt[qm[m]];
+        for (int64_t i = 0; i < nd; ++i) {
+          memcpy(im, s->multi + i * d, sizeof(int) * d);
+          if (im[j] != pj) continue;
+          double ph = 1.0;
+          for (int m = 0; m < d; ++m)
+            if (m != j) ph *= L1[im[m]][qm[m]];
+          s->rhs[i] -= Wf * ph * an * ustar;
+        }
+      }
+    }
+  /* inverse mass */
+  for (int64_t i = 0; i < nd; ++i) out[i] = s->rhs[i];
+  double line[OR_MAXN];
+  if (gauss) {
+    /* out <- (B^{-T})^{x d} out: per dimension y = B^{-T} r */
+    for (int j = 0; j < d; ++j)
+      for (int64_t b = 0; b < nd; ++b) {
+        memcpy(im, s->multi + b * d, sizeof(int) * d);
+        if (im[j] != 0) continue;
+        for (int r = 0; r <= k; ++r) line[r] = out[b + r * g->nstride[j]];
+        for (int q = 0; q <= k; ++q) {
+          double v = 0.0;
+          for (int r = 0; r <= k; ++r) v += g->Binv[r][q] * line[r];
+          out[b + q * g->nstride[j]] = v;
+        }
+      }
+  }
+  for (int64_t q = 0; q < nd; ++q) {
+    memcpy(qm, s->multi + q * d, sizeof(int) * d);
+    double W = 1.0;
+    for (int m = 0; m < d; ++m) W *= wt[qm[m]];
+    out[q] /= W * detJ[q];
+  }
+  if (gauss) {
+    /* out <- (B^{-1})^{x d} out */
+    for (int j = 0; j < d; ++j)
+      for (int64_t b = 0; b < nd; ++b) {
+        memcpy(im, s->multi + b * d, sizeof(int) * d);
+        if (im[j] != 0) continue;
+        for (int r = 0; r <= k; ++r) line[r] = out[b + r * g->nstride[j]];
+        for (int q = 0; q <= k; ++q) {
+          double v = 0.0;
+          for (int r = 0; r <= k; ++r) v += g->Binv[q][r] * line[r];
+          out[b + q * g->nstride[j]] = v;
+        }
+      }
+  }
+  free(detJ);
+}
+
 int or_apply_cells(const or_mesh *mesh, int k, const or_field *field, int mode,
                    const double *u, const int64_t *cells, int64_t ncells,
                    double *out) {
   or_geom g;
   if (setup_geom(mesh, k, &g) || check_field(&g, field)) return -1;
-  if (mode < 0 || mode > 2) return -1;
+  if (mode < 0 || mode > 3 || (mode == 1 && g.eps != 0.0)) return -1;
   for (int64_t t = 0; t < ncells; ++t)
     if (cells[t] < 0 || cells[t] >= g.ncells) return -1;
   int err = 0;
@@ -639,7 +871,11 @@ int or_apply_cells(const or_mesh *mesh, int k, const or_field *field, int mode,
     } else {
 #pragma omp for schedule(dynamic, 4)
       for (int64_t t = 0; t < ncells; ++t) {
-        if (mode == 2)
+        if (mode == 0)
+          eval_cell_general(&g, field, 0, u, cells[t], out + t * g.nd, &s);
+        else if (mode == 3 || (mode == 2 && g.eps != 0.0))
+          eval_cell_general(&g, field, 1, u, cells[t], out + t * g.nd, &s);
+        else if (mode == 2)
           eval_cell_gauss(&g, field, u, cells[t], out + t * g.nd, &s);
         else
           eval_cell(&g, field, mode, u, cells[t], out + t * g.nd, &s);
@@ -802,7 +1038,19 @@ int or_field_sine_table(const or_mesh *mesh, int k, double amp, double *E) {
         int qmm = (int)(nr % g.n);
         cr /= g.cells[m];
         nr /= g.n;
-        double x = g.lo[m] + (cmm + g.xi[qmm]) * g.h[m];
+        (void)cmm;
+        (void)qmm;
+        int cfull[OR_MAXD] = {0}, qfull[OR_MAXD] = {0};
+        {
+          int64_t cr2 = xc, nr2 = xn;
+          for (int mm = 0; mm < g.dx; ++mm) {
+            cfull[mm] = (int)(cr2 % g.cells[mm]);
+            qfull[mm] = (int)(nr2 % g.n);
+            cr2 /= g.cells[mm];
+            nr2 /= g.n;
+          }
+        }
+        double x = node_coord(&g, cfull, qfull, m);
         E[(xc * nxn + xn) * g.dx + m] =
             amp * sin(2.0 * OR_PI * (x - g.lo[m]) / (g.hi[m] - g.lo[m]));
       }
@@ -817,10 +1065,24 @@ int or_diagnostics(const or_mesh *mesh, int k, const double *u, double *mass,
   double ms = 0.0, en = 0.0;
 #pragma omp parallel for reduction(+ : ms, en) schedule(static)
   for (int64_t c = 0; c < g.ncells; ++c) {
-    int qm[OR_MAXD];
+    int qm[OR_MAXD], cm[OR_MAXD];
+    cell_multi(&g, c, cm);
     for (int64_t q = 0; q < g.nd; ++q) {
       node_multi(&g, q, qm);
       double W = vol_weight(&g, qm);
+      if (g.eps != 0.0) {
+        /* times det(dx/dX) of the mapping at the node */
+        double X[OR_MAXD], x[OR_MAXD], Jx[3][3];
+        for (int m = 0; m < g.d; ++m) X[m] = g.lo[m] + (cm[m] + g.xi[qm[m]]) * g.h[m];
+        map_point(&g, X, x, Jx);
+        double dt = Jx[0][0];
+        if (g.dx == 2) dt = Jx[0][0] * Jx[1][1] - Jx[0][1] * Jx[1][0];
+        if (g.dx == 3)
+          dt = Jx[0][0] * (Jx[1][1] * Jx[2][2] - Jx[1][2] * Jx[2][1]) -
+               Jx[0][1] * (Jx[1][0] * Jx[2][2] - Jx[1][2] * Jx[2][0]) +
+               Jx[0][2] * (Jx[1][0] * Jx[2][1] - Jx[1][1] * Jx[2][0]);
+        W *= dt;
+      }
       double v = u[c * g.nd + q];
       ms += W * v;
       en += W * v * v;
@@ -866,7 +1128,7 @@ static double x_point(const or_geom *g, int64_t p, int64_t nxn, double *x) {
 
 int or_vp_density(const or_mesh *mesh, int k, const double *u, double *rho) {
   or_geom g;
-  if (setup_geom(mesh, k, &g) || g.dx != g.dv) return -1;
+  if (setup_geom(mesh, k, &g) || g.eps != 0.0 || g.dx != g.dv) return -1;
   int64_t nxc, nxn, nvc, nvn;
   x_layout(&g, &nxc, &nxn, &nvc, &nvn);
   const int64_t X = nxc * nxn;
@@ -893,7 +1155,7 @@ int or_vp_density(const or_mesh *mesh, int k, const double *u, double *rho) {
 
 int or_vp_field(const or_mesh *mesh, int k, int M, const double *rho, double *E) {
   or_geom g;
-  if (setup_geom(mesh, k, &g) || g.dx != g.dv || M < 1) return -1;
+  if (setup_geom(mesh, k, &g) || g.eps != 0.0 || g.dx != g.dv || M < 1) return -1;
   int64_t nxc, nxn, nvc, nvn;
   x_layout(&g, &nxc, &nxn, &nvc, &nvn);
   const int64_t X = nxc * nxn;
@@ -946,7 +1208,7 @@ int or_vp_field(const or_mesh *mesh, int k, int M, const double *rho, double *E)
 int or_vp_rk_steps(const or_mesh *mesh, int k, int M, int mode, double dt, int nsteps,
                    double *u) {
   or_geom g;
-  if (setup_geom(mesh, k, &g) || g.dx != g.dv) return -1;
+  if (setup_geom(mesh, k, &g) || g.eps != 0.0 || g.dx != g.dv) return -1;
   int64_t nxc, nxn, nvc, nvn;
   x_layout(&g, &nxc, &nxn, &nvc, &nvn);
   const int64_t X = nxc * nxn, N = g.nd * g.ncells;

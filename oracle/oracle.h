@@ -42,6 +42,11 @@ typedef struct {
   int dim_x, dim_v;
   int cells[6];
   double lo[6], hi[6];
+  /* Deformation of the configuration space (the tensor-product mapping of
+   * Sec. 3.1/3.3 with a curved x-mesh and a Cartesian v-mesh): the box point
+   * X maps to x_m = X_m + map_eps L_m prod_{k < dim_x} sin(2 pi (X_k - lo_k)
+   * / L_k), L = hi - lo. 0: Cartesian. |map_eps| <= 0.05. */
+  double map_eps;
 } or_mesh;
 
 /* Advection field.
@@ -82,8 +87,12 @@ int or_gauss_rule(int k, double *g, double *w);
  * basis values skipped; mode 2: the same weak form with Gauss-Legendre
  * quadrature (k+1 points per dimension, full sums, the exactly integrated
  * non-diagonal mass matrix; the E table enters through its nodal
- * interpolant). Every function taking a mode accepts 2. Returns 0, or -1 on
- * invalid input. */
+ * interpolant). Every function taking a mode accepts 2. With a mapping
+ * (map_eps != 0) modes 0 and 2 evaluate the weak form with the metric
+ * terms (contravariant flux |J| J^{-1} a at the quadrature points, the mass
+ * matrix with |J|); mode 1 requires map_eps = 0. Mode 3 is mode 2 through
+ * that general evaluation even without a mapping (for tests). Returns 0,
+ * or -1 on invalid input. */
 int or_apply_cells(const or_mesh *mesh, int k, const or_field *field, int mode,
                    const double *u, const int64_t *cells, int64_t ncells,
                    double *out);
