@@ -185,6 +185,22 @@ hd_status hd_get_field(hd_solver *s, double *E_host, hd_stream stream);
  * quadrature 0 only. */
 hd_status hd_set_quadrature(hd_solver *s, int quadrature);
 
+/* Curved configuration cells: the tensor-product mapping of Sec. 3.1 with a
+ * deformed x-mesh and a Cartesian v-mesh. The box point X maps to
+ *   x_m = X_m + eps (hi_m - lo_m) prod_{k < dim_x} sin(2 pi (X_k - lo_k)/(hi_k - lo_k)),
+ * periodic, identity on the box faces. Node coordinates (initial states,
+ * the sine field) follow the mapping; the operator is the weak form with
+ * the contravariant flux |J| J^{-1} a at the quadrature points and the mass
+ * matrix with |J|; the metric is stored at the x-quadrature points only
+ * (per x-cell) and combined with the v-metric on the fly (Sec. 3.3).
+ * Diagnostics weight with |J|. Works with either quadrature (one cell per
+ * workgroup, as quadrature 1). eps = 0 restores Cartesian cells;
+ * |eps| <= 0.05 (HD_ERR_INVALID otherwise, or if |J| <= 0 somewhere).
+ * HD_ERR_UNSUPPORTED with the Vlasov-Poisson field, where the kernel's LDS
+ * would exceed 160 KiB, and for 5D degree 5 (not compiled). The CFL estimate of hd_stable_dt ignores the
+ * mapping. */
+hd_status hd_set_mapping(hd_solver *s, double eps);
+
 /* For the Vlasov-Poisson field: recompute the device E table from the
  * current state on `stream` (Sec. 6, steps 1-4 of a stage; asynchronous).
  * A no-op for prescribed fields. Requires hd_bind. */

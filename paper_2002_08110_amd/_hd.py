@@ -24,6 +24,7 @@ SYMBOLS = (
     "hd_create", "hd_destroy", "hd_num_dofs", "hd_required_bytes", "hd_bind",
     "hd_set_field_constant", "hd_set_field_phase_space", "hd_set_field_sine",
     "hd_set_field_vlasov_poisson", "hd_get_field", "hd_compute_field", "hd_set_quadrature",
+    "hd_set_mapping",
     "hd_set_state", "hd_init_state", "hd_state_ptr", "hd_get_state", "hd_apply",
     "hd_stable_dt", "hd_rk_stage", "hd_rk_step", "hd_diagnostics", "hd_get_plan",
     "hd_set_plan", "hd_last_error", "hd_batch_create", "hd_batch_destroy",
@@ -84,6 +85,7 @@ def load():
         "hd_get_field": ([vp, P(d), vp], st),
         "hd_compute_field": ([vp, vp], st),
         "hd_set_quadrature": ([vp, i], st),
+        "hd_set_mapping": ([vp, d], st),
         "hd_set_state": ([vp, vp, i, vp], st),
         "hd_init_state": ([vp, i, P(d), vp], st),
         "hd_state_ptr": ([vp, P(vp)], st),

@@ -247,4 +247,26 @@ inline bool make_gauss_tables(const Tables1D &gl, GaussTables1D *t) {
   return true;
 }
 
+// The collocation rule in the same form (the points are the nodes): B =
+// B^{-1} = I, Dg = D, ext[s] = e_{s k}, lift[s][q] = delta_{q, s k} / w_q,
+// for the kernel that evaluates mapped cells with either rule.
+inline void make_gl_quad_tables(const Tables1D &gl, GaussTables1D *t) {
+  const int n = gl.n, k = n - 1;
+  *t = GaussTables1D{};
+  t->n = n;
+  for (int q = 0; q < n; ++q) {
+    t->g[q] = gl.xi[q];
+    t->om[q] = gl.w[q];
+    for (int i = 0; i < n; ++i) {
+      t->B[q * n + i] = q == i ? 1.0 : 0.0;
+      t->Binv[q * n + i] = q == i ? 1.0 : 0.0;
+      t->Dg[q * n + i] = gl.D[q * n + i];
+    }
+  }
+  for (int sd = 0; sd < 2; ++sd) {
+    t->ext[sd][sd * k] = 1.0;
+    t->lift[sd][sd * k] = 1.0 / gl.w[sd * k];
+  }
+}
+
 }  // namespace hd

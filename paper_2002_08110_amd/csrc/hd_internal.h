@@ -40,6 +40,12 @@ struct hd_solver {
   int quad = 0;
   hd::GaussTables1D gtab{};
   bool gtab_ok = false;
+  hd::GaussTables1D gltab{};  // the collocation rule in the same form
+  // Mapped configuration cells: deformation amplitude (0: Cartesian) and the
+  // device metric table (hd::gauss_metric_elems per x-cell).
+  double map_eps = 0.0;
+  size_t off_xmetric = 0;
+  bool mapped() const { return map_eps != 0.0; }
   // Vlasov-Poisson field (field_kind 2): modes per dimension and scratch.
   int vp_modes = 0, vp_groups = 0;
   size_t off_vp_partial = 0, off_vp_wv = 0, off_vp_A = 0, off_vp_B = 0, off_vp_Eh = 0,
@@ -60,6 +66,7 @@ struct hd_solver {
   double2 *vp_Ehat() const { return reinterpret_cast<double2 *>(ws + off_vp_Eh); }
   double2 *vp_mats() const { return reinterpret_cast<double2 *>(ws + off_vp_mats); }
   double *vp_mom() const { return reinterpret_cast<double *>(ws + off_vp_mom); }
+  double *xmetric() const { return reinterpret_cast<double *>(ws + off_xmetric); }
   size_t psize() const { return prec == HD_FP32 ? sizeof(float) : sizeof(double); }
 };
 

@@ -182,10 +182,10 @@ hd_plan default_plan(const hd_solver *s) {
 
 hd::LaunchShape hd::rt::shape_of(const hd_solver *s) {
   hd::LaunchShape ls{};
-  if (s->quad == 1) {
+  if (s->quad == 1 || s->mapped()) {
     ls.grid = (unsigned)s->ncells;
     ls.block = (unsigned)hd::gauss_threads((int)s->nd);
-    ls.shmem = (size_t)hd::gauss_lds_elems(s->d, s->n, s->dx) * s->psize();
+    ls.shmem = (size_t)hd::gauss_lds_elems(s->d, s->n, s->dx, s->mapped()) * s->psize();
     return ls;
   }
   if (s->plan.kernel == 1) {
@@ -218,7 +218,7 @@ namespace rt {
 
 const void *stage_entry(const hd_solver *s) {
   const bool f32 = s->prec == HD_FP32;
-  if (s->quad == 1) return hd::stage_gauss_entry(s->d, s->n, f32);
+  if (s->quad == 1 || s->mapped()) return hd::stage_gauss_entry(s->d, s->n, f32, s->mapped());
   if (s->plan.kernel == 1) return f32 ? hd::stage_k3_f32(s->plan.options)
                                       : hd::stage_k3_f64(s->plan.options);
   const int rd = s->plan.reg_dims, lds = s->plan.lds, n = s->n, sd = s->plan.split_dims,
@@ -266,7 +266,10 @@ template <typename P>
 hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, int mode,
                     int stage, double dt, hipStream_t st) {
   hd::StageParams<P> prm;
-  fill_params<P>(s, &prm, s->plan.kernel);
+  // The sweep kernel (Gauss-Legendre quadrature or mapped cells) reads the
+  // fields in their own form, not the specialised kernel's.
+  const bool sweep = s->quad == 1 || s->mapped();
+  fill_params<P>(s, &prm, sweep ? 0 : s->plan.kernel);
   const hd::LaunchShape ls = hd::rt::shape_of(s);
   prm.nblocks = ls.grid;
   prm.u_in = in;
@@ -296,7 +299,7 @@ hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, in
     const bool moments = mode == 1 && stage > 0 && s->vp_mom_src == in;
     const hd_status vr = hd::rt::vp_enqueue(s, in, st, moments);
     if (vr != HD_OK) return vr;
-    if (mode == 1 && s->quad == 0 && s->plan.kernel == 1 && s->vp_mom_bytes)
+    if (mode == 1 && s->quad == 0 && !s->mapped() && s->plan.kernel == 1 && s->vp_mom_bytes)
       prm.vp_mom = s->vp_mom();
   }
   if (ls.shmem > 65536) {
@@ -306,20 +309,23 @@ hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, in
   }
   hd::GaussTables<P> gt;
   void *args[] = {&prm, &gt};
-  if (s->quad == 1) {
+  if (s->quad == 1 || s->mapped()) {
+    const hd::GaussTables1D &src = s->quad == 1 ? s->gtab : s->gltab;
     const int n = s->n;
     for (int q = 0; q < n * n; ++q) {
-      gt.B[q] = (P)s->gtab.B[q];
-      gt.Binv[q] = (P)s->gtab.Binv[q];
-      gt.Dg[q] = (P)s->gtab.Dg[q];
+      gt.B[q] = (P)src.B[q];
+      gt.Binv[q] = (P)src.Binv[q];
+      gt.Dg[q] = (P)src.Dg[q];
     }
     for (int q = 0; q < n; ++q) {
-      gt.g[q] = (P)s->gtab.g[q];
+      gt.g[q] = (P)src.g[q];
+      gt.om[q] = (P)src.om[q];
       for (int sd = 0; sd < 2; ++sd) {
-        gt.ext[sd][q] = (P)s->gtab.ext[sd][q];
-        gt.lift[sd][q] = (P)s->gtab.lift[sd][q];
+        gt.ext[sd][q] = (P)src.ext[sd][q];
+        gt.lift[sd][q] = (P)src.lift[sd][q];
       }
     }
+    if (s->mapped()) prm.xmetric = s->xmetric();
   }
   hipError_t e = hipLaunchKernel(fn, dim3(ls.grid), dim3(ls.block), args, ls.shmem, st);
   if (e != hipSuccess) return fail(HD_ERR_HIP, std::string("stage kernel launch: ") + hipGetErrorString(e));
@@ -368,7 +374,41 @@ struct GeomArgs {
   double lo[6], hi[6], h[6];
   double xi[8], w[8];
   long long nd, ndofs;
+  double eps;  // x-space deformation
 };
+
+// The deformation of the configuration box: x_m = X_m + eps L_m prod_k
+// sin(theta_k), theta_k = 2 pi (X_k - lo_k) / L_k (m, k < dx); Jx = dx/dX.
+__host__ __device__ inline void map_box_point(int dx, const double *lo, const double *hi,
+                                              double eps, const double *X, double *x,
+                                              double Jx[3][3]) {
+  const double two_pi = 6.283185307179586476925286766559;
+  double sn[3], cs[3], prod = 1.0;
+  for (int k = 0; k < dx; ++k) {
+    const double th = two_pi * (X[k] - lo[k]) / (hi[k] - lo[k]);
+    sn[k] = sin(th);
+    cs[k] = cos(th);
+    prod *= sn[k];
+  }
+  for (int m = 0; m < dx; ++m) {
+    const double Lm = hi[m] - lo[m];
+    x[m] = X[m] + eps * Lm * prod;
+    for (int k = 0; k < dx; ++k) {
+      double p = cs[k];
+      for (int r = 0; r < dx; ++r)
+        if (r != k) p *= sn[r];
+      Jx[m][k] = (m == k ? 1.0 : 0.0) + eps * Lm * two_pi / (hi[k] - lo[k]) * p;
+    }
+  }
+}
+
+__host__ __device__ inline double det_small(int n, const double A[3][3]) {
+  if (n == 1) return A[0][0];
+  if (n == 2) return A[0][0] * A[1][1] - A[0][1] * A[1][0];
+  return A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+         A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+         A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+}
 
 __global__ void init_kernel(GeomArgs g, int kind, double alpha, double *u) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -381,6 +421,10 @@ __global__ void init_kernel(GeomArgs g, int kind, double alpha, double *u) {
     const int q = (int)(node % g.n);
     node /= g.n;
     x[j] = g.lo[j] + (c + g.xi[q]) * g.h[j];
+  }
+  if (g.eps != 0.0) {
+    double X[3] = {x[0], x[1], x[2]}, J[3][3];
+    map_box_point(g.dx, g.lo, g.hi, g.eps, X, x, J);
   }
   const double two_pi = 6.283185307179586476925286766559;
   double v;
@@ -406,11 +450,19 @@ __global__ void __launch_bounds__(kDiagThreads) diag_kernel1(GeomArgs g, const d
   const long long b1 = min(b0 + chunk, g.ndofs);
   double m = 0.0, e = 0.0;
   for (long long i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
-    long long node = i % g.nd;
-    double W = 1.0;
+    long long node = i % g.nd, cell = i / g.nd;
+    double W = 1.0, X[3];
     for (int j = 0; j < g.d; ++j) {
-      W *= g.h[j] * g.w[node % g.n];
+      const int q = (int)(node % g.n);
+      W *= g.h[j] * g.w[q];
+      if (j < 3) X[j] = g.lo[j] + ((double)(cell % g.cells[j]) + g.xi[q]) * g.h[j];
       node /= g.n;
+      cell /= g.cells[j];
+    }
+    if (g.eps != 0.0) {  // times det(dx/dX) at the node
+      double x[3], J[3][3];
+      map_box_point(g.dx, g.lo, g.hi, g.eps, X, x, J);
+      W *= det_small(g.dx, J);
     }
     const double v = u[i];
     m += W * v;
@@ -472,7 +524,89 @@ GeomArgs geom_of(const hd_solver *s) {
   }
   g.nd = s->nd;
   g.ndofs = s->ndofs;
+  g.eps = s->map_eps;
   return g;
+}
+
+// Metric of the mapped x-cells at the current quadrature points (layout of
+// hd::gauss_metric_elems), uploaded to the device table.
+hd_status upload_metric(hd_solver *s) {
+  if (!s->mapped() || !s->ws) return HD_OK;
+  const int n = s->n, dx = s->dx;
+  const double *pt = s->quad == 1 ? s->gtab.g : s->tab.xi;
+  int64_t nxc = 1, nxn = 1;
+  for (int j = 0; j < dx; ++j) {
+    nxc *= s->mesh.cells[j];
+    nxn *= n;
+  }
+  const int per = hd::gauss_metric_elems(n, dx), nfx = (int)(nxn / n);
+  std::vector<double> tab((size_t)(nxc * per));
+  // A = Jx diag(h_x) at the reference point xi of x-cell c: adj(A), det(A)
+  auto metric = [&](const int *c, const double *xi, double adj[3][3], double *det) {
+    double X[3] = {0, 0, 0}, x[3], J[3][3];
+    for (int m = 0; m < dx; ++m) X[m] = s->mesh.lo[m] + (c[m] + xi[m]) * s->h[m];
+    map_box_point(dx, s->mesh.lo, s->mesh.hi, s->map_eps, X, x, J);
+    double A[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    for (int m = 0; m < dx; ++m)
+      for (int k = 0; k < dx; ++k) A[m][k] = J[m][k] * s->h[k];
+    *det = det_small(dx, A);
+    if (dx == 1) {
+      adj[0][0] = 1.0;
+    } else if (dx == 2) {
+      adj[0][0] = A[1][1];
+      adj[0][1] = -A[0][1];
+      adj[1][0] = -A[1][0];
+      adj[1][1] = A[0][0];
+    } else {
+      for (int r = 0; r < 3; ++r)
+        for (int cc = 0; cc < 3; ++cc) {
+          const int r1 = (cc + 1) % 3, r2 = (cc + 2) % 3, c1 = (r + 1) % 3, c2 = (r + 2) % 3;
+          adj[r][cc] = A[r1][c1] * A[r2][c2] - A[r1][c2] * A[r2][c1];
+        }
+    }
+  };
+  double dmin = 1e300;
+  for (int64_t xc = 0; xc < nxc; ++xc) {
+    int c[3] = {0, 0, 0};
+    int64_t r = xc;
+    for (int m = 0; m < dx; ++m) {
+      c[m] = (int)(r % s->mesh.cells[m]);
+      r /= s->mesh.cells[m];
+    }
+    double *out = tab.data() + xc * per;
+    for (int64_t xq = 0; xq < nxn; ++xq) {
+      double xi[3] = {0, 0, 0}, adj[3][3], det;
+      int64_t rr = xq;
+      for (int m = 0; m < dx; ++m) {
+        xi[m] = pt[rr % n];
+        rr /= n;
+      }
+      metric(c, xi, adj, &det);
+      dmin = std::min(dmin, det);
+      for (int a = 0; a < dx; ++a)
+        for (int b = 0; b < dx; ++b) out[xq * (dx * dx + 1) + a * dx + b] = adj[a][b];
+      out[xq * (dx * dx + 1) + dx * dx] = det;
+    }
+    double *face = out + nxn * (dx * dx + 1);
+    for (int j = 0; j < dx; ++j)
+      for (int sd = 0; sd < 2; ++sd)
+        for (int xp = 0; xp < nfx; ++xp) {
+          double xi[3] = {0, 0, 0}, adj[3][3], det;
+          int rr = xp;
+          for (int m = 0; m < dx; ++m) {
+            if (m == j) continue;
+            xi[m] = pt[rr % n];
+            rr /= n;
+          }
+          xi[j] = sd ? 1.0 : 0.0;
+          metric(c, xi, adj, &det);
+          dmin = std::min(dmin, det);
+          for (int k = 0; k < dx; ++k) face[((j * 2 + sd) * nfx + xp) * dx + k] = adj[j][k];
+        }
+  }
+  if (!(dmin > 0.0)) return fail(HD_ERR_INVALID, "the mapping is not invertible on this mesh");
+  HD_HIP(hipMemcpy(s->xmetric(), tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+  return HD_OK;
 }
 
 // Device E table: the phase-space E at the x-nodes, or for a constant field
@@ -574,6 +708,7 @@ hd_status hd_create(const hd_mesh *mesh, int degree, int prec, hd_solver **out) 
     return fail(HD_ERR_INVALID, "Gauss-Lobatto table construction failed");
   }
   s->gtab_ok = hd::make_gauss_tables(s->tab, &s->gtab);
+  hd::make_gl_quad_tables(s->tab, &s->gltab);
   int64_t nxc = 1, nxn = 1;
   for (int j = 0; j < s->dx; ++j) {
     nxc *= mesh->cells[j];
@@ -593,6 +728,8 @@ hd_status hd_create(const hd_mesh *mesh, int degree, int prec, hd_solver **out) 
   s->off_part = off;
   off = align_up(off + sizeof(double) * (2 * kDiagBlocks + 2));
   off = hd::rt::vp_layout(s, off);
+  s->off_xmetric = off;
+  off = align_up(off + sizeof(double) * (size_t)(nxc * hd::gauss_metric_elems(s->n, s->dx)));
   s->total = off;
   s->plan = default_plan(s);
   *out = s;
@@ -628,6 +765,8 @@ hd_status hd_bind(hd_solver *s, void *ws, size_t bytes) {
   s->ws = reinterpret_cast<char *>(ws);
   s->cur = 0;
   HD_HIP(hipMemset(s->ws, 0, s->total));
+  hd_status r = upload_metric(s);
+  if (r) return r;
   return upload_E(s);
 }
 
@@ -673,7 +812,18 @@ hd_status hd_set_field_sine(hd_solver *s, double amp, double sign) {
         const int q = (int)(nr % s->n);
         cr /= s->mesh.cells[j];
         nr /= s->n;
-        const double x = s->mesh.lo[j] + (c + s->tab.xi[q]) * s->h[j];
+        double x = s->mesh.lo[j] + (c + s->tab.xi[q]) * s->h[j];
+        if (s->mapped()) {
+          double X[3] = {0, 0, 0}, xm[3], J[3][3];
+          int64_t cr2 = xc, nr2 = xn;
+          for (int m = 0; m < s->dx; ++m) {
+            X[m] = s->mesh.lo[m] + ((double)(cr2 % s->mesh.cells[m]) + s->tab.xi[nr2 % s->n]) * s->h[m];
+            cr2 /= s->mesh.cells[m];
+            nr2 /= s->n;
+          }
+          map_box_point(s->dx, s->mesh.lo, s->mesh.hi, s->map_eps, X, xm, J);
+          x = xm[j];
+        }
         E[(size_t)((xc * nxn + xn) * s->dx + j)] =
             amp * std::sin(two_pi * (x - s->mesh.lo[j]) / (s->mesh.hi[j] - s->mesh.lo[j]));
       }
@@ -684,6 +834,7 @@ hd_status hd_set_field_sine(hd_solver *s, double amp, double sign) {
 hd_status hd_set_field_vlasov_poisson(hd_solver *s, int modes) {
   if (!s) return fail(HD_ERR_INVALID, "NULL argument");
   if (s->dx != s->dv) return fail(HD_ERR_INVALID, "Vlasov-Poisson field needs dim_x == dim_v");
+  if (s->mapped()) return fail(HD_ERR_UNSUPPORTED, "the Vlasov-Poisson field needs Cartesian cells");
   hd_status r = check_bound(s);
   if (r) return r;
   if (modes < 1 || modes > hd::rt::kVpMaxModes)
@@ -708,7 +859,24 @@ hd_status hd_set_quadrature(hd_solver *s, int quadrature) {
   }
   s->quad = quadrature;
   changed(s);
-  return HD_OK;
+  return upload_metric(s);
+}
+
+hd_status hd_set_mapping(hd_solver *s, double eps) {
+  if (!s) return fail(HD_ERR_INVALID, "NULL argument");
+  if (!(std::fabs(eps) <= 0.05)) return fail(HD_ERR_INVALID, "|eps| must be at most 0.05");
+  if (eps != 0.0 && s->field_kind == 2)
+    return fail(HD_ERR_UNSUPPORTED, "the Vlasov-Poisson field needs Cartesian cells");
+  if (eps != 0.0 && !hd::stage_gauss_entry(s->d, s->n, s->prec == HD_FP32, true))
+    return fail(HD_ERR_UNSUPPORTED,
+                "the mapped-cell kernel holds two cell-sized arrays, a face layer and the "
+                "x-metric in LDS: this (d, degree, precision) exceeds 160 KiB");
+  const double old = s->map_eps;
+  s->map_eps = eps;
+  changed(s);
+  hd_status r = upload_metric(s);
+  if (r) s->map_eps = old;
+  return r;
 }
 
 hd_status hd_compute_field(hd_solver *s, hd_stream stream) {

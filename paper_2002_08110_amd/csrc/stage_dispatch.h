@@ -133,8 +133,9 @@ const void *stage_d6_f32(int n, int rd, int lds, int sd, int opt, int ld);
 const void *stage_k3_f64(int options);
 const void *stage_k3_f32(int options);
 
-// Gauss-Legendre quadrature kernel (stage_gauss.hip): one cell per
-// workgroup; nullptr where the cell's LDS does not fit.
-const void *stage_gauss_entry(int d, int n, bool f32);
+// Sweep kernel (stage_gauss.hip): Gauss-Legendre quadrature on Cartesian
+// cells, or either quadrature on mapped cells; one cell per workgroup;
+// nullptr where the cell's LDS does not fit.
+const void *stage_gauss_entry(int d, int n, bool f32, bool mapped = false);
 
 }  // namespace hd

@@ -35,14 +35,24 @@ struct GaussTables {
   P ext[2][kMaxN];
   P lift[2][kMaxN];
   P g[kMaxN];
+  P om[kMaxN];
 };
 
 // Up to 1024 threads: few nodes per thread keep the per-node registers (the
 // accumulated stage operator, u and du) small.
 constexpr int gauss_threads(int nd) { return nd >= 256 ? 256 : (nd + 63) / 64 * 64; }
 
-// Elements of the 1D tables (B, B^{-1}, Dg, ext, lift, g).
-constexpr int gauss_table_elems(int n) { return 3 * n * n + 5 * n; }
+// Elements of the 1D tables (B, B^{-1}, Dg, ext, lift, g, om).
+constexpr int gauss_table_elems(int n) { return 3 * n * n + 6 * n; }
+
+// Metric of a mapped x-cell (the tensor-product mapping keeps it in x-space:
+// O(#x-cells) storage, combined with the Cartesian v-metric on the fly):
+// at each x-quadrature point xq, adj(A) (dx x dx, row-major) and det(A) for
+// A = d x / d xi of the x-block; then, for each x-dimension j and side s, at
+// the face's tangential x-points, row j of adj(A) on that face.
+constexpr int gauss_metric_elems(int n, int dx) {
+  return ipow(n, dx) * (dx * dx + 1) + dx * 2 * ipow(n, dx - 1) * dx;
+}
 
 // LDS arrays are padded by one element after every n^2: a thread's n x n
 // plane then starts n^2 + 1 elements after its neighbour's, which spreads
@@ -52,10 +62,10 @@ __host__ __device__ constexpr int gauss_pad(int q) { return q + q / (N * N); }
 constexpr int gauss_padded(int n, int count) { return count + count / (n * n) + 1; }
 
 // LDS elements of P: U and the accumulator Y (n^d each), one face layer,
-// E at the x-Gauss points and the 1D tables.
-constexpr int gauss_lds_elems(int d, int n, int dx) {
+// E at the x-Gauss points, the 1D tables and, for mapped cells, the metric.
+constexpr int gauss_lds_elems(int d, int n, int dx, bool mapped = false) {
   return 2 * gauss_padded(n, ipow(n, d)) + gauss_padded(n, ipow(n, d - 1)) + ipow(n, dx) * dx +
-         gauss_table_elems(n);
+         gauss_table_elems(n) + (mapped ? gauss_metric_elems(n, dx) : 0);
 }
 
 // In place along one axis (stride = N^axis) of an N-ary array of `total`
@@ -135,7 +145,14 @@ __device__ __forceinline__ void gauss_transform(P *buf, const P *M, int t, int T
   }
 }
 
-template <int D, int N, int DX, typename P>
+// MAPPED: the weak form on mapped cells, with the contravariant flux
+// ahat = |J| J^{-1} a at the quadrature points (the x-metric from the table,
+// the v-metric diag(h)), upwind traces u* on every face, and the mass matrix
+// with |J|:
+//   Y(q) = [ sum_j sum_m Dg[m][q_j] om_m ahat_j U (along j) / om_{q_j}
+//            - sum_s lift_s[q_j] (ahat_j n_s u*)(p) ] / |J(q)|,
+// then L(u) = (B^{-1})^{x d} Y. The tables may be the collocation ones.
+template <int D, int N, int DX, typename P, bool MAPPED = false>
 __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
     stage_gauss_kernel(const StageParams<P> prm, const GaussTables<P> gt) {
   constexpr int ND = ipow(N, D), NF = ND / N, T = gauss_threads(ND);
@@ -149,7 +166,10 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
   // compile-time indices: a kernel argument indexed per lane would be copied
   // whole to scratch.
   P *tB = EG + NXN * DX, *tBinv = tB + N * N, *tDg = tBinv + N * N;
-  P *tExt = tDg + N * N, *tLift = tExt + 2 * N, *tG = tLift + 2 * N;
+  P *tExt = tDg + N * N, *tLift = tExt + 2 * N, *tG = tLift + 2 * N, *tOm = tG + N;
+  constexpr int MXE = DX * DX + 1, NFX = NXN / N;
+  P *MX = tOm + N;                 // [xq][MXE] (mapped cells)
+  P *MF = MX + NXN * MXE;          // [j][side][face x-point][DX]
   const int t = threadIdx.x;
   if (t == 0) {
 #pragma unroll
@@ -165,6 +185,7 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
       tLift[i] = gt.lift[0][i];
       tLift[N + i] = gt.lift[1][i];
       tG[i] = gt.g[i];
+      tOm[i] = gt.om[i];
     }
   }
   unsigned cell = blockIdx.x;
@@ -182,15 +203,22 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
   const bool stage = prm.mode == 1;
   const double *ucell = prm.u_in + (uint64_t)cell * ND;
   for (int q = t; q < ND; q += T) W[gauss_pad<N>(q)] = (P)ucell[q];
+  unsigned xcell = 0, xs = 1;
+#pragma unroll
+  for (int m = 0; m < DX; ++m) {
+    xcell += c[m] * xs;
+    xs *= prm.cells[m];
+  }
+  P detv = P(1);
+  if constexpr (MAPPED) {
+    const double *mt = prm.xmetric + (uint64_t)xcell * gauss_metric_elems(N, DX);
+    for (int i = t; i < gauss_metric_elems(N, DX); i += T) MX[i] = (P)mt[i];
+#pragma unroll
+    for (int m = DX; m < D; ++m) detv *= prm.vh[m];
+  }
   __syncthreads();  // tables ready
   if (phase) {
     // E at the x-Gauss points: the nodal interpolant of the cell's E table
-    unsigned xcell = 0, xs = 1;
-#pragma unroll
-    for (int m = 0; m < DX; ++m) {
-      xcell += c[m] * xs;
-      xs *= prm.cells[m];
-    }
     const P *e = prm.E + (uint64_t)xcell * NXN * DX;
     for (int idx = t; idx < NXN * DX; idx += T) {
       const int xq = idx / DX, comp = idx % DX;
@@ -222,6 +250,99 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
     }
     return EG[(q % NXN) * DX + (j - DX)];
   };
+  // ahat_j at the cell point q (mapped cells)
+  auto ahat_at = [&](int j, int q) -> P {
+    const P *mx = MX + (q % NXN) * MXE;
+    if (j < DX) {
+      P s = P(0);
+#pragma unroll
+      for (int k2 = 0; k2 < DX; ++k2) s += mx[j * DX + k2] * a_at(k2, q);
+      return detv * s;
+    }
+    return mx[DX * DX] * detv * prm.inv_h[j] * a_at(j, q);
+  };
+  // ahat_j at the point with index q (digit j ignored) on face `side` of
+  // dimension j
+  auto ahat_face = [&](int j, int side, int q) -> P {
+    if (j < DX) {
+      const int sj = ipow(N, j), xq = q % NXN;
+      const int xp = xq % sj + (xq / (sj * N)) * sj;
+      const P *mf = MF + ((j * 2 + side) * NFX + xp) * DX;
+      P s = P(0);
+#pragma unroll
+      for (int k2 = 0; k2 < DX; ++k2) s += mf[k2] * a_at(k2, q);
+      return detv * s;
+    }
+    return ahat_at(j, q);
+  };
+
+  if constexpr (MAPPED) {
+    // volume (weak form), one dimension per sweep
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const int sj = ipow(N, j);
+      for (int l = t; l < NF; l += T) {
+        const int base = l % sj + (l / sj) * sj * N;
+        P tv[N];
+#pragma unroll
+        for (int m = 0; m < N; ++m)
+          tv[m] = tOm[m] * ahat_at(j, base + m * sj) * W[gauss_pad<N>(base + m * sj)];
+#pragma unroll
+        for (int qq = 0; qq < N; ++qq) {
+          P s = tDg[qq] * tv[0];
+#pragma unroll
+          for (int m = 1; m < N; ++m) s += tDg[m * N + qq] * tv[m];
+          s /= tOm[qq];
+          if (j == 0) Yb[gauss_pad<N>(base + qq * sj)] = s;
+          else Yb[gauss_pad<N>(base + qq * sj)] += s;
+        }
+      }
+      __syncthreads();
+    }
+    // faces: every side contributes - lift (ahat.n) u*
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const int sj = ipow(N, j);
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        int inflow = 0;
+        for (int p = t; p < NF; p += T) {
+          const P a = ahat_face(j, side, p % sj + (p / sj) * sj * N);
+          inflow |= side ? (a < P(0)) : (a > P(0));
+        }
+        const bool nbr = __syncthreads_or(inflow);
+        if (nbr) {
+          const double *un = prm.u_in + (uint64_t)(side ? right[j] : left[j]) * ND;
+          for (int p = t; p < NF; p += T) {
+            const int node = p % sj + (side ? 0 : N - 1) * sj + (p / sj) * sj * N;
+            F[gauss_pad<N>(p)] = (P)un[node];
+          }
+          __syncthreads();
+          gauss_transform<N, D - 1>(F, tB, t, T);
+        }
+        for (int p = t; p < NF; p += T) {
+          const int base = p % sj + (p / sj) * sj * N;
+          P uo = P(0);
+#pragma unroll
+          for (int m = 0; m < N; ++m) uo += tExt[side * N + m] * W[gauss_pad<N>(base + m * sj)];
+          const P a = ahat_face(j, side, base);
+          const P an = side ? a : -a;
+          const P us = (an >= P(0) || !nbr) ? uo : F[gauss_pad<N>(p)];
+          F[gauss_pad<N>(p)] = an * us;
+        }
+        __syncthreads();
+        for (int q = t; q < ND; q += T) {
+          const int qj = (q / sj) % N;
+          const int p = q % sj + (q / (sj * N)) * sj;
+          Yb[gauss_pad<N>(q)] -= tLift[side * N + qj] * F[gauss_pad<N>(p)];
+        }
+        __syncthreads();
+      }
+    }
+    // inverse of |J|
+    for (int q = t; q < ND; q += T) Yb[gauss_pad<N>(q)] /= MX[(q % NXN) * MXE + DX * DX] * detv;
+    __syncthreads();
+  } else {
 
   // volume: Y = - sum_j a_j / h_j Dg_j U, two dimensions per pass (each
   // thread owns an N x N plane), the odd one last
@@ -320,6 +441,7 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
       __syncthreads();  // F is free again
     }
   }
+  }  // Cartesian cells
   // L(u) = (B^{-1} x ... x B^{-1}) Y
   gauss_transform<N, D>(Yb, tBinv, t, T);
 

@@ -80,6 +80,9 @@ struct StageParams {
   // otherwise.
   double *vp_mom;
   double gw[kMaxN];     // Gauss-Lobatto weights on [0, 1]
+  // Mapped configuration cells: per x-cell, the metric at the quadrature
+  // points (layout in stage_gauss.h); null for Cartesian cells.
+  const double *xmetric;
 };
 
 // Map the hardware workgroup id (dispatched round-robin over the 8 XCDs) to a

@@ -119,6 +119,10 @@ class Solver:
         q = {"gauss_lobatto": 0, "gauss_legendre": 1}[quadrature]
         check(self.lib.hd_set_quadrature(self.h, q))
 
+    def set_mapping(self, eps):
+        """Deform the configuration mesh (0: Cartesian); see hd_set_mapping."""
+        check(self.lib.hd_set_mapping(self.h, float(eps)))
+
     def compute_field(self, stream=None):
         """Recompute the device E table of the Vlasov-Poisson field from the
         current state (asynchronous; no-op for prescribed fields)."""
