@@ -43,13 +43,16 @@ def parse():
     ap.add_argument("--precisions", default="fp64,fp32")
     ap.add_argument("--plan", default="", help="override plan, e.g. lds=1,reg_dims=1")
     ap.add_argument("--mode", default="bench",
-                    choices=["bench", "stages", "copy", "batch", "serve", "vp", "gauss"],
+                    choices=["bench", "stages", "copy", "batch", "serve", "vp", "gauss", "mapped"],
                     help="stages: only run --steps x 5 stage launches per precision (for "
                          "profilers); copy: a plain device copy of --copy-mib MiB (the "
                          "calibration kernel for the byte counters); batch: the 96-solve "
                          "mix; serve: a prefix of the seeded request trace; vp: the 6D "
                          "Vlasov-Poisson stage (self-consistent field each stage); gauss: "
-                         "the workload with Gauss-Legendre quadrature beside collocation")
+                         "the workload with Gauss-Legendre quadrature beside collocation; "
+                         "mapped: the workload on a deformed configuration mesh")
+    ap.add_argument("--map-eps", type=float, default=0.02,
+                    help="mapped: deformation amplitude of the configuration mesh")
     ap.add_argument("--quadrature", default="gauss_lobatto",
                     choices=["gauss_lobatto", "gauss_legendre"],
                     help="stages: quadrature of the profiled run")
@@ -118,12 +121,15 @@ def run_copy(mib):
           % (mib, ms, 2 * n * 8 / ms / 1e6), file=sys.stderr, flush=True)
 
 
-def measure(case, precision, steps, warmup, plan_override, quadrature="gauss_lobatto"):
+def measure(case, precision, steps, warmup, plan_override, quadrature="gauss_lobatto",
+            map_eps=0.0):
     import torch
 
     from paper_2002_08110_amd.solver import Solver
     S = Solver(case.dim_x, case.dim_v, case.cells, case.lo, case.hi, case.degree,
                precision=precision)
+    if map_eps:
+        S.set_mapping(map_eps)  # before the field: node coordinates follow the mapping
     if case.field == "sine":
         S.set_field_sine(case.amp)
     else:
@@ -171,7 +177,8 @@ def measure(case, precision, steps, warmup, plan_override, quadrature="gauss_lob
         dof_updates_per_s=S.ndofs * 5 / (ms_step * 1e-3),
         stage_ms=[round(float(x), 4) for x in stage_ms],
         stage_kernel_GBps=achieved, algorithmic_bytes_per_dof=float(np.mean(stage_bytes(psize))),
-        plan=S.get_plan() if quadrature == "gauss_lobatto" else "stage_gauss_kernel",
+        plan=(S.get_plan() if quadrature == "gauss_lobatto" and not map_eps
+              else "stage_gauss_kernel"),
         quadrature=quadrature, mass_drift=(m1 - m0) / abs(m0), energy_ratio=e1 / e0,
     )
     S.close()
@@ -387,6 +394,40 @@ def run_gauss(case, steps, warmup, precisions):
     print(json.dumps(out), flush=True)
 
 
+def run_mapped(case, steps, warmup, precisions, eps):
+    """The workload on a deformed configuration mesh (hd_set_mapping eps),
+    with Gauss-Legendre quadrature (the paper's default discretization) and
+    with collocation. Prints one JSON line."""
+    n, dx = case.degree + 1, case.dim_x
+    nxc = int(np.prod(case.cells[:dx]))
+    metric_bytes = nxc * (n ** dx * (dx * dx + 1) + dx * 2 * n ** (dx - 1) * dx) * 8
+    full_bytes = case.ndofs * (case.d ** 2 + 1) * 8
+    out = {"metric": "6D k=3 DoF-updates/s per RK stage on a deformed configuration mesh",
+           "unit": "DoF-updates/s", "workload": case.name, "map_eps": eps,
+           "metric_table_bytes": metric_bytes, "per_dof_jacobian_bytes": full_bytes,
+           "paper_context": {"value": PAPER_GDOFS_PER_NODE * 1e9, "unit": "DoF-updates/s",
+                             "hardware": "1 SuperMUC-NG node, FP64, Gauss quadrature, "
+                                         "deformed mesh"},
+           "modes": {}}
+    for prec in precisions:
+        for quad in ("gauss_legendre", "gauss_lobatto"):
+            r = measure(case, prec, steps, warmup, {}, quadrature=quad, map_eps=eps)
+            out["modes"]["%s_%s" % (prec, quad)] = {
+                k: r[k] for k in ("dof_updates_per_s", "ms_per_step", "stage_ms",
+                                  "stage_kernel_GBps", "mass_drift")}
+            print("# %s %s mapped: %.1f GDoF/s, stage ms %s, mass drift %.1e"
+                  % (prec, quad, r["dof_updates_per_s"] / 1e9, r["stage_ms"], r["mass_drift"]),
+                  file=sys.stderr, flush=True)
+    head = out["modes"].get("fp64_gauss_legendre") or next(iter(out["modes"].values()))
+    out["value"] = head["dof_updates_per_s"]
+    out["vs_paper_node"] = head["dof_updates_per_s"] / (PAPER_GDOFS_PER_NODE * 1e9)
+    gb = head["stage_kernel_GBps"]
+    out["roofline"] = {"bound": "lds", "kernel": "stage_gauss_kernel<6,4,3,double,mapped>",
+                       "achieved_hbm": gb, "peak_hbm": HBM_PEAK_GBPS, "unit": "GB/s",
+                       "frac_hbm": gb / HBM_PEAK_GBPS, "algorithmic_bytes_per_dof": 28.8}
+    print(json.dumps(out), flush=True)
+
+
 def profiled_kernel(precision, plan_override):
     """The committed counter profile of the default plan's stage kernel
     (bytes per launch, VALU activity), or None if the kernel source changed
@@ -468,6 +509,9 @@ def main():
         return
     if args.mode == "gauss":
         run_gauss(case, args.steps, args.warmup, args.precisions.split(","))
+        return
+    if args.mode == "mapped":
+        run_mapped(case, args.steps, args.warmup, args.precisions.split(","), args.map_eps)
         return
     if args.mode == "stages":
         for prec in args.precisions.split(","):
