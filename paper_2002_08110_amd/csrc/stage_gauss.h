@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
     stage_gauss_kernel(const StageParams<P> prm, const GaussTables<P> gt) {
   constexpr int ND = ipow(N, D), NF = ND / N, T = gauss_threads(ND);
   constexpr int NXN = ipow(N, DX);
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];  // 16: FP64 arrays after static LDS
   P *W = reinterpret_cast<P *>(smem_raw);      // the cell, then U
   P *Yb = W + gauss_padded(N, ND);             // the operator at the Gauss points, then L(u)
   P *F = Yb + gauss_padded(N, ND);             // one face layer
@@ -237,9 +237,6 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
       EG[idx] = prm.esign * s;
     }
   }
-  // U = (B x ... x B) u
-  gauss_transform<N, D>(W, tB, t, T);
-
   // a_j at the point with index q (its digit j is not used: a_j does not
   // depend on x_j)
   auto a_at = [&](int j, int q) -> P {
@@ -250,6 +247,47 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
     }
     return EG[(q % NXN) * DX + (j - DX)];
   };
+  // Cartesian cells: which face sides have inflow Gauss points (bit 2 j +
+  // side), and the neighbour layers of one such side per dimension loaded
+  // into registers now, so that their latency overlaps the transform.
+  constexpr int RF = (NF + T - 1) / T;
+  __shared__ int active_mask;
+  int active = 0;
+  int pre_side[D];
+  double pre[MAPPED ? 1 : D][MAPPED ? 1 : RF];
+  if constexpr (!MAPPED) {
+    if (t == 0) active_mask = 0;
+    __syncthreads();  // EG ready, mask cleared
+    int mine = 0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const int sj = ipow(N, j);
+      for (int p = t; p < NF; p += T) {
+        const P a = a_at(j, p % sj + (p / sj) * sj * N);
+        mine |= (a > P(0) ? 1 : 0) << (2 * j);
+        mine |= (a < P(0) ? 1 : 0) << (2 * j + 1);
+      }
+    }
+    if (mine) atomicOr(&active_mask, mine);
+    __syncthreads();
+    active = active_mask;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const int sj = ipow(N, j);
+      pre_side[j] = (active >> (2 * j)) & 1 ? 0 : ((active >> (2 * j + 1)) & 1 ? 1 : -1);
+      if (pre_side[j] < 0) continue;
+      const double *un = prm.u_in + (uint64_t)(pre_side[j] ? right[j] : left[j]) * ND;
+#pragma unroll
+      for (int r = 0; r < RF; ++r) {
+        const int p = t + T * r;
+        const int node = p % sj + (pre_side[j] ? 0 : N - 1) * sj + (p / sj) * sj * N;
+        pre[j][r] = p < NF ? un[node] : 0.0;
+      }
+    }
+  }
+  // U = (B x ... x B) u
+  gauss_transform<N, D>(W, tB, t, T);
+
   // ahat_j at the cell point q (mapped cells)
   auto ahat_at = [&](int j, int q) -> P {
     const P *mx = MX + (q % NXN) * MXE;
@@ -343,104 +381,84 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
     for (int q = t; q < ND; q += T) Yb[gauss_pad<N>(q)] /= MX[(q % NXN) * MXE + DX * DX] * detv;
     __syncthreads();
   } else {
-
-  // volume: Y = - sum_j a_j / h_j Dg_j U, two dimensions per pass (each
-  // thread owns an N x N plane), the odd one last
+    // Per dimension j: the faces' scaled upwind jumps at their Gauss points,
+    // then one sweep along j that adds the volume term - a_j / h_j Dg_j U
+    // and lifts the jump into Y (a lift spreads along j only). When both
+    // sides have inflow points, the first is lifted in a pass of its own.
+    bool ystarted = false;  // Y has been written (uniform)
 #pragma unroll
-  for (int j = 0; j + 1 < D; j += 2) {
-    const int sj = ipow(N, j);
-    const P ih0 = prm.inv_h[j], ih1 = prm.inv_h[j + 1];
-    for (int l = t; l < ND / (N * N); l += T) {
-      const int base = l % sj + (l / sj) * sj * N * N;
-      P v[N][N];
+    for (int j = 0; j < D; ++j) {
+      const int sj = ipow(N, j);
+      const P ih = prm.inv_h[j];
+      int pending = -1;  // side whose jumps wait in F for the sweep (uniform)
 #pragma unroll
-      for (int a = 0; a < N; ++a)
-#pragma unroll
-        for (int b = 0; b < N; ++b) v[a][b] = W[gauss_pad<N>(base + a * sj + b * sj * N)];
-#pragma unroll
-      for (int a = 0; a < N; ++a)
-#pragma unroll
-        for (int b = 0; b < N; ++b) {
-          P d0 = tDg[a * N] * v[0][b], d1 = tDg[b * N] * v[a][0];
-#pragma unroll
-          for (int m = 1; m < N; ++m) {
-            d0 += tDg[a * N + m] * v[m][b];
-            d1 += tDg[b * N + m] * v[a][m];
+      for (int side = 0; side < 2; ++side) {
+        // A side none of whose Gauss points is inflow contributes nothing.
+        if (!((active >> (2 * j + side)) & 1)) continue;
+        if (pending >= 0) {
+          for (int q = t; q < ND; q += T) {
+            const int qj = (q / sj) % N;
+            const int p = q % sj + (q / (sj * N)) * sj;
+            const P y = ih * tLift[pending * N + qj] * F[gauss_pad<N>(p)];
+            if (ystarted) Yb[gauss_pad<N>(q)] += y;
+            else Yb[gauss_pad<N>(q)] = y;
           }
-          const int q = base + a * sj + b * sj * N;
-          const P y = -(a_at(j, q) * ih0 * d0 + a_at(j + 1, q) * ih1 * d1);
-          if (j == 0) Yb[gauss_pad<N>(q)] = y;
-          else Yb[gauss_pad<N>(q)] += y;
+          ystarted = true;
+          __syncthreads();
         }
+        // side 0 (face xi_j = 0): the left neighbour's layer i_j = k;
+        // side 1 (xi_j = 1): the right neighbour's layer i_j = 0. The layer
+        // of the prefetched side is already in registers.
+        if (side == pre_side[j]) {
+#pragma unroll
+          for (int r = 0; r < RF; ++r) {
+            const int p = t + T * r;
+            if (p < NF) F[gauss_pad<N>(p)] = (P)pre[j][r];
+          }
+        } else {
+          const double *un = prm.u_in + (uint64_t)(side ? right[j] : left[j]) * ND;
+          for (int p = t; p < NF; p += T) {
+            const int node = p % sj + (side ? 0 : N - 1) * sj + (p / sj) * sj * N;
+            F[gauss_pad<N>(p)] = (P)un[node];
+          }
+        }
+        __syncthreads();
+        gauss_transform<N, D - 1>(F, tB, t, T);
+        for (int p = t; p < NF; p += T) {
+          const int base = p % sj + (p / sj) * sj * N;
+          P uo = P(0);
+#pragma unroll
+          for (int m = 0; m < N; ++m) uo += tExt[side * N + m] * W[gauss_pad<N>(base + m * sj)];
+          const P a = a_at(j, base);
+          const P an = side ? a : -a;
+          F[gauss_pad<N>(p)] = (an < P(0) ? an : P(0)) * (uo - F[gauss_pad<N>(p)]);
+        }
+        __syncthreads();
+        pending = side;
+      }
+      // the sweep along j: line l has the tangential index l of the layer
+      for (int l = t; l < NF; l += T) {
+        const int base = l % sj + (l / sj) * sj * N;
+        P v[N];
+#pragma unroll
+        for (int m = 0; m < N; ++m) v[m] = W[gauss_pad<N>(base + m * sj)];
+        const P coef = -a_at(j, base) * ih;
+        const P fj = pending >= 0 ? ih * F[gauss_pad<N>(l)] : P(0);
+#pragma unroll
+        for (int qq = 0; qq < N; ++qq) {
+          P s = tDg[qq * N] * v[0];
+#pragma unroll
+          for (int m = 1; m < N; ++m) s += tDg[qq * N + m] * v[m];
+          P y = coef * s;
+          if (pending >= 0) y += tLift[pending * N + qq] * fj;
+          const int q = gauss_pad<N>(base + qq * sj);
+          if (ystarted) Yb[q] += y;
+          else Yb[q] = y;
+        }
+      }
+      ystarted = true;
+      __syncthreads();  // Y complete for this dimension; F is free again
     }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int j = D - (D % 2); j < D; ++j) {
-    const int sj = ipow(N, j);
-    const P ih = prm.inv_h[j];
-    for (int l = t; l < NF; l += T) {
-      const int lo = l % sj, hi = l / sj;
-      const int base = lo + hi * sj * N;
-      P v[N];
-#pragma unroll
-      for (int m = 0; m < N; ++m) v[m] = W[gauss_pad<N>(base + m * sj)];
-      const P coef = -a_at(j, base) * ih;
-#pragma unroll
-      for (int qq = 0; qq < N; ++qq) {
-        P s = tDg[qq * N] * v[0];
-#pragma unroll
-        for (int m = 1; m < N; ++m) s += tDg[qq * N + m] * v[m];
-        if (j == 0) Yb[gauss_pad<N>(base + qq * sj)] = coef * s;
-        else Yb[gauss_pad<N>(base + qq * sj)] += coef * s;
-      }
-    }
-    __syncthreads();
-  }
-
-  // faces: per dimension and side, the neighbour's nodal layer carried to
-  // the face Gauss points, the scaled upwind jump, lifted into Y
-#pragma unroll
-  for (int j = 0; j < D; ++j) {
-    const int sj = ipow(N, j);
-    const P ih = prm.inv_h[j];
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      // A side none of whose Gauss points is inflow contributes nothing (one
-      // side per dimension where a_j keeps its sign over the face).
-      int inflow = 0;
-      for (int p = t; p < NF; p += T) {
-        const P a = a_at(j, p % sj + (p / sj) * sj * N);
-        inflow |= side ? (a < P(0)) : (a > P(0));
-      }
-      if (!__syncthreads_or(inflow)) continue;
-      // side 0 (face xi_j = 0): the left neighbour's layer i_j = k;
-      // side 1 (xi_j = 1): the right neighbour's layer i_j = 0
-      const double *un = prm.u_in + (uint64_t)(side ? right[j] : left[j]) * ND;
-      for (int p = t; p < NF; p += T) {
-        const int node = p % sj + (side ? 0 : N - 1) * sj + (p / sj) * sj * N;
-        F[gauss_pad<N>(p)] = (P)un[node];
-      }
-      __syncthreads();
-      gauss_transform<N, D - 1>(F, tB, t, T);
-      for (int p = t; p < NF; p += T) {
-        const int base = p % sj + (p / sj) * sj * N;
-        P uo = P(0);
-#pragma unroll
-        for (int m = 0; m < N; ++m) uo += tExt[side * N + m] * W[gauss_pad<N>(base + m * sj)];
-        const P a = a_at(j, base);
-        const P an = side ? a : -a;
-        F[gauss_pad<N>(p)] = (an < P(0) ? an : P(0)) * (uo - F[gauss_pad<N>(p)]);
-      }
-      __syncthreads();
-      for (int q = t; q < ND; q += T) {
-        const int qj = (q / sj) % N;
-        const int p = q % sj + (q / (sj * N)) * sj;
-        Yb[gauss_pad<N>(q)] += ih * tLift[side * N + qj] * F[gauss_pad<N>(p)];
-      }
-      __syncthreads();  // F is free again
-    }
-  }
   }  // Cartesian cells
   // L(u) = (B^{-1} x ... x B^{-1}) Y
   gauss_transform<N, D>(Yb, tBinv, t, T);
