@@ -166,3 +166,42 @@ def test_unsupported_gauss_cases_raise():
         with pytest.raises(HDError):
             S.set_quadrature("gauss_legendre")
         S.close()
+
+
+def test_batch_mixing_quadratures_and_mapped_cells_equals_alone():
+    from paper_2002_08110_amd.solver import Batch
+    cases = [W.phase_space_case("p", 2, 2, [3, 2, 2, 3], 3, 3),
+             W.phase_space_case("q", 3, 3, [2, 1, 1, 1, 2, 1], 2, 3),
+             W.phase_space_case("r", 1, 1, [6, 5], 4, 3),
+             W.phase_space_case("s", 2, 2, [2, 3, 2, 2], 2, 3)]
+    setups = [("gauss_lobatto", 0.0, "fp64"), ("gauss_legendre", 0.0, "fp64"),
+              ("gauss_lobatto", 0.02, "fp64"), ("gauss_legendre", 0.03, "fp32")]
+
+    def make(case, quad, eps, prec):
+        S = gpu_solver(case, prec)
+        if quad == "gauss_legendre":
+            S.set_quadrature(quad)
+        if eps:
+            S.set_mapping(eps)
+            S.set_field_sine(case.amp)
+        S.init_state(case.ic, list(case.ic_params))
+        return S
+
+    alone, dts = [], []
+    for c, (q, e, p) in zip(cases, setups):
+        S = make(c, q, e, p)
+        dt = S.stable_dt(0.2)
+        dts.append(dt)
+        S.rk_step(dt, 3)
+        alone.append(S.get_state())
+        S.close()
+    solvers = [make(c, q, e, p) for c, (q, e, p) in zip(cases, setups)]
+    B = Batch(solvers)
+    for _ in range(3):
+        B.step(dts)
+    torch.cuda.synchronize()
+    for S, a in zip(solvers, alone):
+        assert np.array_equal(S.get_state(), a)
+    B.close()
+    for S in solvers:
+        S.close()
