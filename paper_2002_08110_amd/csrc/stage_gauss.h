@@ -247,47 +247,6 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
     }
     return EG[(q % NXN) * DX + (j - DX)];
   };
-  // Cartesian cells: which face sides have inflow Gauss points (bit 2 j +
-  // side), and the neighbour layers of one such side per dimension loaded
-  // into registers now, so that their latency overlaps the transform.
-  constexpr int RF = (NF + T - 1) / T;
-  __shared__ int active_mask;
-  int active = 0;
-  int pre_side[D];
-  double pre[MAPPED ? 1 : D][MAPPED ? 1 : RF];
-  if constexpr (!MAPPED) {
-    if (t == 0) active_mask = 0;
-    __syncthreads();  // EG ready, mask cleared
-    int mine = 0;
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-      const int sj = ipow(N, j);
-      for (int p = t; p < NF; p += T) {
-        const P a = a_at(j, p % sj + (p / sj) * sj * N);
-        mine |= (a > P(0) ? 1 : 0) << (2 * j);
-        mine |= (a < P(0) ? 1 : 0) << (2 * j + 1);
-      }
-    }
-    if (mine) atomicOr(&active_mask, mine);
-    __syncthreads();
-    active = active_mask;
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-      const int sj = ipow(N, j);
-      pre_side[j] = (active >> (2 * j)) & 1 ? 0 : ((active >> (2 * j + 1)) & 1 ? 1 : -1);
-      if (pre_side[j] < 0) continue;
-      const double *un = prm.u_in + (uint64_t)(pre_side[j] ? right[j] : left[j]) * ND;
-#pragma unroll
-      for (int r = 0; r < RF; ++r) {
-        const int p = t + T * r;
-        const int node = p % sj + (pre_side[j] ? 0 : N - 1) * sj + (p / sj) * sj * N;
-        pre[j][r] = p < NF ? un[node] : 0.0;
-      }
-    }
-  }
-  // U = (B x ... x B) u
-  gauss_transform<N, D>(W, tB, t, T);
-
   // ahat_j at the cell point q (mapped cells)
   auto ahat_at = [&](int j, int q) -> P {
     const P *mx = MX + (q % NXN) * MXE;
@@ -313,6 +272,59 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
     }
     return ahat_at(j, q);
   };
+  // Which face sides have inflow Gauss points (bit 2 j + side), and the
+  // neighbour layers of one such side per dimension loaded into registers
+  // now, so that their latency overlaps the transform.
+  // (Only while that holds at most 32 values per thread: beyond it the layers
+  // would spill.)
+  constexpr int RF = (NF + T - 1) / T;
+  constexpr bool kPre = D * RF <= 32;
+  __shared__ int active_mask;
+  int active = 0;
+  int pre_side[D];
+  double pre[kPre ? D : 1][kPre ? RF : 1];
+  {
+    if (t == 0) active_mask = 0;
+    __syncthreads();  // EG ready, mask cleared
+    int mine = 0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const int sj = ipow(N, j);
+      for (int p = t; p < NF; p += T) {
+        const int q = p % sj + (p / sj) * sj * N;
+        if constexpr (MAPPED && !kPre) {
+          mine = (1 << (2 * D)) - 1;  // every side may have inflow points
+        } else if constexpr (MAPPED) {
+          mine |= (ahat_face(j, 0, q) > P(0) ? 1 : 0) << (2 * j);
+          mine |= (ahat_face(j, 1, q) < P(0) ? 1 : 0) << (2 * j + 1);
+        } else {
+          const P a = a_at(j, q);
+          mine |= (a > P(0) ? 1 : 0) << (2 * j);
+          mine |= (a < P(0) ? 1 : 0) << (2 * j + 1);
+        }
+      }
+    }
+    if (mine) atomicOr(&active_mask, mine);
+    __syncthreads();
+    active = active_mask;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const int sj = ipow(N, j);
+      pre_side[j] = (active >> (2 * j)) & 1 ? 0 : ((active >> (2 * j + 1)) & 1 ? 1 : -1);
+      if constexpr (!kPre) pre_side[j] = -1;
+      if (pre_side[j] < 0) continue;
+      const double *un = prm.u_in + (uint64_t)(pre_side[j] ? right[j] : left[j]) * ND;
+#pragma unroll
+      for (int r = 0; r < RF; ++r) {
+        const int p = t + T * r;
+        const int node = p % sj + (pre_side[j] ? 0 : N - 1) * sj + (p / sj) * sj * N;
+        pre[kPre ? j : 0][kPre ? r : 0] = p < NF ? un[node] : 0.0;
+      }
+    }
+  }
+  // U = (B x ... x B) u
+  gauss_transform<N, D>(W, tB, t, T);
+
 
   if constexpr (MAPPED) {
     // volume (weak form), one dimension per sweep
@@ -343,17 +355,20 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
       const int sj = ipow(N, j);
 #pragma unroll
       for (int side = 0; side < 2; ++side) {
-        int inflow = 0;
-        for (int p = t; p < NF; p += T) {
-          const P a = ahat_face(j, side, p % sj + (p / sj) * sj * N);
-          inflow |= side ? (a < P(0)) : (a > P(0));
-        }
-        const bool nbr = __syncthreads_or(inflow);
+        const bool nbr = (active >> (2 * j + side)) & 1;
         if (nbr) {
-          const double *un = prm.u_in + (uint64_t)(side ? right[j] : left[j]) * ND;
-          for (int p = t; p < NF; p += T) {
-            const int node = p % sj + (side ? 0 : N - 1) * sj + (p / sj) * sj * N;
-            F[gauss_pad<N>(p)] = (P)un[node];
+          if (side == pre_side[j]) {
+#pragma unroll
+            for (int r = 0; r < RF; ++r) {
+              const int p = t + T * r;
+              if (p < NF) F[gauss_pad<N>(p)] = (P)pre[kPre ? j : 0][kPre ? r : 0];
+            }
+          } else {
+            const double *un = prm.u_in + (uint64_t)(side ? right[j] : left[j]) * ND;
+            for (int p = t; p < NF; p += T) {
+              const int node = p % sj + (side ? 0 : N - 1) * sj + (p / sj) * sj * N;
+              F[gauss_pad<N>(p)] = (P)un[node];
+            }
           }
           __syncthreads();
           gauss_transform<N, D - 1>(F, tB, t, T);
@@ -413,7 +428,7 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
 #pragma unroll
           for (int r = 0; r < RF; ++r) {
             const int p = t + T * r;
-            if (p < NF) F[gauss_pad<N>(p)] = (P)pre[j][r];
+            if (p < NF) F[gauss_pad<N>(p)] = (P)pre[kPre ? j : 0][kPre ? r : 0];
           }
         } else {
           const double *un = prm.u_in + (uint64_t)(side ? right[j] : left[j]) * ND;
