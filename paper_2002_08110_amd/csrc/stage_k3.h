@@ -6,10 +6,14 @@
 // Derivative sweeps: dims 5 and 6 act on the thread's registers; dims 1 and 2
 // exchange values between lanes of a wave with DPP (quad broadcast, row
 // rotation); dims 3 and 4 read the cell staged in LDS. All global loads of a
-// cell - its own values, the stage increment and the six inflow face layers
-// of its neighbours - are issued before the first use, so the cell pays one
-// memory latency; the face layers are spread evenly over the threads and
-// passed to their owners through LDS.
+// cell - its own values and the six inflow face layers of its neighbours -
+// are issued before the first use, so the cell pays one memory latency; the
+// stage increment follows and overlaps the arithmetic. The face layers are
+// spread evenly over the threads. Those of dims 5 and 6 land in the threads
+// that use them; those of dims 1 to 4 pass to their users through LDS, and
+// the face terms are taken before the sweeps so that the cell can then
+// overwrite the layers: 32 KiB of LDS per workgroup in FP64, which lets
+// three workgroups share a CU.
 //
 // The operator is the one of stage_kernel.h (strong form of the collocated
 // weak form, upwind inflow jump, diagonal inverse mass folded in); the RK
@@ -22,11 +26,12 @@ namespace hd {
 
 constexpr int kK3Nodes = 4096;
 constexpr int kK3Face = 1024;
-// LDS: the cell plus one inflow layer per dimension.
+// LDS: the four face layers of dims 1 to 4, then the cell in the same space.
 template <typename P>
 constexpr size_t k3_lds_bytes() {
-  return (size_t)(kK3Nodes + 6 * kK3Face) * sizeof(P);
+  return (size_t)kK3Nodes * sizeof(P);
 }
+static_assert(4 * kK3Face == kK3Nodes, "face layers and cell share the LDS");
 
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double x) {
@@ -51,11 +56,11 @@ __device__ __forceinline__ int k3_face_node0(int p, int j) {
   return (p & lowmask) | ((p & ~lowmask) << 2);
 }
 
-// Register budget per thread that the LDS footprint allows anyway: FP64 (80
-// KiB of LDS) runs 2 workgroups per CU = 2 waves per SIMD; FP32 (40 KiB) 4.
+// Register budget per thread: FP64 runs 3 workgroups per CU = 3 waves per
+// SIMD (at most 168 VGPRs; 4 would spill), FP32 4.
 template <typename P>
 constexpr int k3_waves_per_eu() {
-  return sizeof(P) == 8 ? 2 : 4;
+  return sizeof(P) == 8 ? 3 : 4;
 }
 
 // Plan options (hd_plan.options): bit 0 (kOptStream, stage_kernel.h)
@@ -72,7 +77,7 @@ __device__ __forceinline__ void stage_k3_body(const StageParams<P> &prm, unsigne
   constexpr bool KEEPU = (OPT & kOptKeepU64) != 0 && sizeof(P) == 4;
   constexpr int N = 4, ND = kK3Nodes, F = kK3Face;
   P *cellb = reinterpret_cast<P *>(smem_raw);
-  P *faceb = cellb + ND;
+  P *faceb = cellb;  // layers of dims 1-4 first, then the cell
   const int t = threadIdx.x;
   const int l = t & 63;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -150,32 +155,116 @@ __device__ __forceinline__ void stage_k3_body(const StageParams<P> &prm, unsigne
     }
   }
   sched_fence();
-  // ---- phase B: stage the cell and the layers in LDS ----
+  // ---- phase B: the face layers of dims 1-4 in LDS ----
   if (lds_reuse) __syncthreads();
   P u[16];
 #pragma unroll
-  for (int s = 0; s < 16; ++s) {
-    u[s] = to_p<P>(ud[s]);
-    cellb[t + 256 * s] = u[s];
-  }
+  for (int s = 0; s < 16; ++s) u[s] = to_p<P>(ud[s]);
 #pragma unroll
-  for (int j = 0; j < 6; ++j)
+  for (int j = 0; j < 4; ++j)
 #pragma unroll
     for (int q = 0; q < 4; ++q) faceb[j * F + t + 256 * q] = to_p<P>(fv[j][q]);
   __syncthreads();
-  // The stage increment is loaded now; its latency overlaps the sweeps.
+  // The stage increment is loaded now; its latency overlaps the arithmetic.
   P *ducell = prm.du + (uint64_t)cell * ND;
   P dv[16];
   if (stage && prm.read_du) {
 #pragma unroll
     for (int s = 0; s < 16; ++s) dv[s] = ld_opt<NT>(ducell + t + 256 * s);
   }
-
-  // ---- phase C: sweeps ----
   P acc[16];
 #pragma unroll
   for (int s = 0; s < 16; ++s) acc[s] = P(0);
 #define Dm prm.Dm
+  // ---- inflow faces ----
+  // Branch-free: every thread reads the layer entry of each of its nodes and
+  // weights it by zero unless the node lies on that dimension's inflow face.
+  // Dims 1-4 read the layers from LDS, dims 5 and 6 from the registers that
+  // loaded them: face node t + 256 q of dim 5 lies on this thread's nodes
+  // s = 4 q (i5 = 0) and 4 q + 3 (i5 = 3), of dim 6 on s = q and 12 + q.
+  {
+    // dim 1: a = v_1(i4); face index p = node >> 2
+    const P a = ax(0, w);
+    const P wt = ((i1 == 0 && a > P(0)) ? a : ((i1 == 3 && a < P(0)) ? -a : P(0))) *
+                 prm.lift_inv_h[0];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) acc[s] += wt * (faceb[0 * F + (t >> 2) + 64 * s] - u[s]);
+  }
+#pragma unroll
+  for (int z = 0; z < 16; ++z) pin(acc[z]);
+  sched_fence();
+  {
+    // dim 2: a = v_2(i5); p = (node & 3) + 4 (node >> 4)
+    const int pb = (t & 3) + 4 * (t >> 4);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const P a = ax(1, s & 3);
+      const P wt = ((i2 == 0 && a > P(0)) ? a : ((i2 == 3 && a < P(0)) ? -a : P(0))) *
+                   prm.lift_inv_h[1];
+      acc[s] += wt * (faceb[1 * F + pb + 64 * s] - u[s]);
+    }
+  }
+#pragma unroll
+  for (int z = 0; z < 16; ++z) pin(acc[z]);
+  sched_fence();
+  {
+    // dim 3: a = v_3(i6); p = (node & 15) + 16 (node >> 6)
+    const int pb = (t & 15) + 16 * (t >> 6);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const P a = ax(2, s >> 2);
+      const P wt = ((i3 == 0 && a > P(0)) ? a : ((i3 == 3 && a < P(0)) ? -a : P(0))) *
+                   prm.lift_inv_h[2];
+      acc[s] += wt * (faceb[2 * F + pb + 64 * s] - u[s]);
+    }
+  }
+#pragma unroll
+  for (int z = 0; z < 16; ++z) pin(acc[z]);
+  sched_fence();
+  {
+    // dim 4: a = E_1 (per lane), i4 = wave (uniform); p = l + 64 s
+    const P a = ev[0];
+    if (w == 0 || w == 3) {
+      const P wt = ((w == 0 && a > P(0)) ? a : ((w == 3 && a < P(0)) ? -a : P(0))) *
+                   prm.lift_inv_h[3];
+#pragma unroll
+      for (int s = 0; s < 16; ++s) acc[s] += wt * (faceb[3 * F + l + 64 * s] - u[s]);
+    }
+  }
+#pragma unroll
+  for (int z = 0; z < 16; ++z) pin(acc[z]);
+  sched_fence();
+  {
+    // dim 5: i5 = s & 3, a = E_2; p = t + 256 i6; inflow node i5 = 0 (a > 0) or 3 (a < 0)
+    const P a = ev[1];
+    const P wl = a > P(0) ? a * prm.lift_inv_h[4] : P(0);
+    const P wr = a < P(0) ? -a * prm.lift_inv_h[4] : P(0);
+#pragma unroll
+    for (int i6 = 0; i6 < 4; ++i6) {
+      const P fvv = to_p<P>(fv[4][i6]);
+      acc[4 * i6] += wl * (fvv - u[4 * i6]);
+      acc[4 * i6 + 3] += wr * (fvv - u[4 * i6 + 3]);
+    }
+  }
+  {
+    // dim 6: i6 = s >> 2, a = E_3; p = t + 256 i5
+    const P a = ev[2];
+    const P wl = a > P(0) ? a * prm.lift_inv_h[5] : P(0);
+    const P wr = a < P(0) ? -a * prm.lift_inv_h[5] : P(0);
+#pragma unroll
+    for (int i5 = 0; i5 < 4; ++i5) {
+      const P fvv = to_p<P>(fv[5][i5]);
+      acc[i5] += wl * (fvv - u[i5]);
+      acc[12 + i5] += wr * (fvv - u[12 + i5]);
+    }
+  }
+
+  // ---- the cell in LDS, over the consumed layers ----
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < 16; ++s) cellb[t + 256 * s] = u[s];
+  __syncthreads();
+  // ---- phase C: sweeps ----
   // dims 5 and 6 (registers): a_{v_2} = ev[1], a_{v_3} = ev[2] are per thread
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
@@ -274,86 +363,6 @@ __device__ __forceinline__ void stage_k3_body(const StageParams<P> &prm, unsigne
     }
   }
   sched_fence();
-  // ---- inflow faces (layers from LDS) ----
-  // Branch-free: every thread reads the layer entry of each of its nodes and
-  // weights it by zero unless the node lies on that dimension's inflow face.
-  {
-    // dim 1: a = v_1(i4); face index p = node >> 2
-    const P a = ax(0, w);
-    const P wt = ((i1 == 0 && a > P(0)) ? a : ((i1 == 3 && a < P(0)) ? -a : P(0))) *
-                 prm.lift_inv_h[0];
-#pragma unroll
-    for (int s = 0; s < 16; ++s) acc[s] += wt * (faceb[0 * F + (t >> 2) + 64 * s] - u[s]);
-  }
-#pragma unroll
-  for (int z = 0; z < 16; ++z) pin(acc[z]);
-  sched_fence();
-  {
-    // dim 2: a = v_2(i5); p = (node & 3) + 4 (node >> 4)
-    const int pb = (t & 3) + 4 * (t >> 4);
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const P a = ax(1, s & 3);
-      const P wt = ((i2 == 0 && a > P(0)) ? a : ((i2 == 3 && a < P(0)) ? -a : P(0))) *
-                   prm.lift_inv_h[1];
-      acc[s] += wt * (faceb[1 * F + pb + 64 * s] - u[s]);
-    }
-  }
-#pragma unroll
-  for (int z = 0; z < 16; ++z) pin(acc[z]);
-  sched_fence();
-  {
-    // dim 3: a = v_3(i6); p = (node & 15) + 16 (node >> 6)
-    const int pb = (t & 15) + 16 * (t >> 6);
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const P a = ax(2, s >> 2);
-      const P wt = ((i3 == 0 && a > P(0)) ? a : ((i3 == 3 && a < P(0)) ? -a : P(0))) *
-                   prm.lift_inv_h[2];
-      acc[s] += wt * (faceb[2 * F + pb + 64 * s] - u[s]);
-    }
-  }
-#pragma unroll
-  for (int z = 0; z < 16; ++z) pin(acc[z]);
-  sched_fence();
-  {
-    // dim 4: a = E_1 (per lane), i4 = wave (uniform); p = l + 64 s
-    const P a = ev[0];
-    if (w == 0 || w == 3) {
-      const P wt = ((w == 0 && a > P(0)) ? a : ((w == 3 && a < P(0)) ? -a : P(0))) *
-                   prm.lift_inv_h[3];
-#pragma unroll
-      for (int s = 0; s < 16; ++s) acc[s] += wt * (faceb[3 * F + l + 64 * s] - u[s]);
-    }
-  }
-#pragma unroll
-  for (int z = 0; z < 16; ++z) pin(acc[z]);
-  sched_fence();
-  {
-    // dim 5: i5 = s & 3, a = E_2; p = t + 256 i6; inflow node i5 = 0 (a > 0) or 3 (a < 0)
-    const P a = ev[1];
-    const P wl = a > P(0) ? a * prm.lift_inv_h[4] : P(0);
-    const P wr = a < P(0) ? -a * prm.lift_inv_h[4] : P(0);
-#pragma unroll
-    for (int i6 = 0; i6 < 4; ++i6) {
-      const P fvv = faceb[4 * F + t + 256 * i6];
-      acc[4 * i6] += wl * (fvv - u[4 * i6]);
-      acc[4 * i6 + 3] += wr * (fvv - u[4 * i6 + 3]);
-    }
-  }
-  {
-    // dim 6: i6 = s >> 2, a = E_3; p = t + 256 i5
-    const P a = ev[2];
-    const P wl = a > P(0) ? a * prm.lift_inv_h[5] : P(0);
-    const P wr = a < P(0) ? -a * prm.lift_inv_h[5] : P(0);
-#pragma unroll
-    for (int i5 = 0; i5 < 4; ++i5) {
-      const P fvv = faceb[5 * F + t + 256 * i5];
-      acc[i5] += wl * (fvv - u[i5]);
-      acc[12 + i5] += wr * (fvv - u[12 + i5]);
-    }
-  }
-
   // ---- phase D: output / RK update ----
   if (!stage) {
     P *ocell = prm.out + (uint64_t)cell * ND;
