@@ -97,7 +97,9 @@ hd::LaunchShape shape_of(const hd_solver *s);
 
 // Entry of the compiled stage kernel of the solver's plan; nullptr if none
 // is compiled.
-const void *stage_entry(const hd_solver *s);
+// The stage kernel of the solver's plan; k3_role selects the 6D degree-3
+// kernel's variant (0 general, 1 first stage, 2 last stage).
+const void *stage_entry(const hd_solver *s, int k3_role = 0);
 
 // Enqueue the five fused stages of one RK step of s on st, starting from
 // solution buffer `par` (the solution ends in buffer 1 - par). s->cur is

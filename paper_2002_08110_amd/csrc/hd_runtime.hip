@@ -216,11 +216,11 @@ hd::LaunchShape hd::rt::shape_of(const hd_solver *s) {
 namespace hd {
 namespace rt {
 
-const void *stage_entry(const hd_solver *s) {
+const void *stage_entry(const hd_solver *s, int k3_role) {
   const bool f32 = s->prec == HD_FP32;
   if (s->quad == 1 || s->mapped()) return hd::stage_gauss_entry(s->d, s->n, f32, s->mapped());
-  if (s->plan.kernel == 1) return f32 ? hd::stage_k3_f32(s->plan.options)
-                                      : hd::stage_k3_f64(s->plan.options);
+  if (s->plan.kernel == 1) return f32 ? hd::stage_k3_f32(s->plan.options, k3_role)
+                                      : hd::stage_k3_f64(s->plan.options, k3_role);
   const int rd = s->plan.reg_dims, lds = s->plan.lds, n = s->n, sd = s->plan.split_dims,
             opt = s->plan.options, ld = s->plan.loop_dims;
   switch (s->d) {
@@ -289,7 +289,9 @@ hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, in
   if ((uint64_t)ls.grid * ls.block >= (uint64_t(1) << 32))
     return fail(HD_ERR_UNSUPPORTED, "stage launch exceeds 2^32 work-items; use a plan with more "
                                     "nodes per thread");
-  const void *fn = hd::rt::stage_entry(s);
+  // The first stage reads no increment, the last writes none.
+  const int k3_role = mode == 1 && !prm.read_du ? 1 : (mode == 1 && !prm.write_du ? 2 : 0);
+  const void *fn = hd::rt::stage_entry(s, k3_role);
   if (!fn) return fail(HD_ERR_HIP, "no compiled stage kernel for this plan");
   if (s->field_kind == 2) {
     // The Vlasov-Poisson field of this stage's input, into the E table. The

@@ -56,11 +56,19 @@ __device__ __forceinline__ int k3_face_node0(int p, int j) {
   return (p & lowmask) | ((p & ~lowmask) << 2);
 }
 
-// Register budget per thread: FP64 runs 3 workgroups per CU = 3 waves per
-// SIMD (at most 168 VGPRs; 4 would spill), FP32 4.
-template <typename P>
+// Stage roles, each compiled separately: the general kernel (operator
+// application and the middle stages), the first stage (no increment to read:
+// its registers are free) and the last stage (the increment is loaded only
+// for the update, as nothing overlaps it there anyway).
+constexpr int kK3General = 0, kK3First = 1, kK3Last = 2;
+
+// Register budget per thread. The general FP64 kernel holds the increment
+// through the sweeps and runs 3 workgroups per CU = 3 waves per SIMD (at most
+// 168 VGPRs; 4 would spill); without that, the first and last stages fit 128
+// VGPRs and run 4. FP32: 4.
+template <typename P, int ROLE>
 constexpr int k3_waves_per_eu() {
-  return sizeof(P) == 8 ? 3 : 4;
+  return sizeof(P) == 8 ? (ROLE == kK3General ? 3 : 4) : 4;
 }
 
 // Plan options (hd_plan.options): bit 0 (kOptStream, stage_kernel.h)
@@ -69,12 +77,15 @@ constexpr int k3_waves_per_eu() {
 // of re-reading it.
 constexpr int kOptKeepU64 = 2;
 
-// One workgroup's cell `cell` (lds_reuse as in stage_body).
-template <typename P, int OPT>
+// One workgroup's cell `cell` (lds_reuse as in stage_body) in stage role
+// ROLE; the first-stage role requires read_du == 0.
+template <typename P, int OPT, int ROLE>
 __device__ __forceinline__ void stage_k3_body(const StageParams<P> &prm, unsigned cell,
                                               unsigned char *smem_raw, bool lds_reuse) {
   constexpr bool NT = (OPT & kOptStream) != 0;
   constexpr bool KEEPU = (OPT & kOptKeepU64) != 0 && sizeof(P) == 4;
+  constexpr bool EARLY_DU = ROLE == kK3General;  // increment loaded before the sweeps
+  constexpr bool ANY_DU = ROLE != kK3First;
   constexpr int N = 4, ND = kK3Nodes, F = kK3Face;
   P *cellb = reinterpret_cast<P *>(smem_raw);
   P *faceb = cellb;  // layers of dims 1-4 first, then the cell
@@ -168,7 +179,7 @@ __device__ __forceinline__ void stage_k3_body(const StageParams<P> &prm, unsigne
   // The stage increment is loaded now; its latency overlaps the arithmetic.
   P *ducell = prm.du + (uint64_t)cell * ND;
   P dv[16];
-  if (stage && prm.read_du) {
+  if (EARLY_DU && stage && prm.read_du) {
 #pragma unroll
     for (int s = 0; s < 16; ++s) dv[s] = ld_opt<NT>(ducell + t + 256 * s);
   }
@@ -370,7 +381,11 @@ __device__ __forceinline__ void stage_k3_body(const StageParams<P> &prm, unsigne
     for (int s = 0; s < 16; ++s) ocell[t + 256 * s] = acc[s];
     return;
   }
-  if (prm.read_du) {
+  if (!EARLY_DU && ANY_DU && prm.read_du) {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) dv[s] = ld_opt<NT>(ducell + t + 256 * s);
+  }
+  if (ANY_DU && prm.read_du) {
 #pragma unroll
     for (int s = 0; s < 16; ++s) dv[s] = prm.rk_a * dv[s] + prm.dt * acc[s];
   } else {
@@ -400,14 +415,14 @@ __device__ __forceinline__ void stage_k3_body(const StageParams<P> &prm, unsigne
   if (prm.vp_mom) prm.vp_mom[(uint64_t)cell * 256 + t] = mom;
 }
 
-template <typename P, int OPT>
+template <typename P, int OPT, int ROLE>
 __global__ void __launch_bounds__(256)
-    __attribute__((amdgpu_waves_per_eu(k3_waves_per_eu<P>(), k3_waves_per_eu<P>())))
+    __attribute__((amdgpu_waves_per_eu(k3_waves_per_eu<P, ROLE>(), k3_waves_per_eu<P, ROLE>())))
     stage_k3_kernel(const StageParams<P> prm) {
   extern __shared__ unsigned char smem_raw[];
   unsigned cell = blockIdx.x;
   if (prm.xcd_remap) cell = xcd_tile(cell, prm.nblocks);
-  stage_k3_body<P, OPT>(prm, cell, smem_raw, false);
+  stage_k3_body<P, OPT, ROLE>(prm, cell, smem_raw, false);
 }
 
 #undef Dm

@@ -193,6 +193,41 @@ class Solver:
             setattr(p, k, int(v))
         check(self.lib.hd_set_plan(self.h, ctypes.byref(p)))
 
+    def tune_plan(self, dt, reps=2, stream=None) -> dict:
+        """Time every candidate plan of this (d, k, precision) on this
+        solver's own mesh and field - `reps` RK steps each, after one untimed
+        step - and keep the fastest. The cell order that suits the caches
+        depends on the mesh, not only on (d, k). The solution is restored
+        from a device copy afterwards (one extra state vector of memory for
+        the duration); the stage increment is left undefined, which the next
+        step's first stage never reads. Returns the chosen plan."""
+        from . import autotune
+        st = torch.cuda.current_stream() if stream is None else stream
+        saved = self.state_tensor().clone()
+        best = None
+        for plan in autotune.candidate_plans(self.d, self.k, self.dim_v, self.precision):
+            try:
+                self.set_plan(**plan)
+            except _hd.HDError:
+                continue
+            self.rk_step(dt, 1, stream=st)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            self.rk_step(dt, reps, stream=st)
+            e1.record(st)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            if best is None or ms < best[0]:
+                best = (ms, self.get_plan())
+        if best is None:
+            raise RuntimeError("no candidate plan is valid for this solver")
+        self.set_plan(**best[1])
+        self.set_state(saved, stream=st)
+        st.synchronize()
+        del saved
+        return best[1]
+
     def apply_tuned_plan(self, cache=None, arch=None) -> bool:
         """Set the plan the autotuner measured fastest for this (d, k,
         precision) on this GPU architecture, if the cache holds one."""

@@ -267,3 +267,25 @@ def test_invalid_arguments_are_rejected_on_device_calls():
     u = torch.zeros(S.ndofs, dtype=torch.float64, device="cuda")
     with pytest.raises(HDError):
         S.apply(u, out=u)  # in and out must not alias
+
+
+@pytest.mark.parametrize("d,k,precision", [(6, 3, "fp64"), (6, 3, "fp32"), (4, 2, "fp64")])
+def test_tune_plan_keeps_the_state_and_steps_as_the_fixed_plan(d, k, precision):
+    # Timing the candidate plans on the solver's own mesh must leave its
+    # solution untouched; afterwards it steps exactly as a solver given the
+    # chosen plan directly.
+    case = small_case(d, k, "sine" if W.SPLITS[d][0] == W.SPLITS[d][1] else "constant")
+    S = gpu_solver(case, precision)
+    u0 = W.random_state(S.ndofs, seed=31)
+    S.set_state(u0)
+    dt = S.stable_dt(0.2)
+    plan = S.tune_plan(dt)
+    assert plan == S.get_plan()
+    assert np.array_equal(S.get_state(), u0)
+    S.rk_step(dt, 2)
+    T = gpu_solver(case, precision, plan=plan)
+    T.set_state(u0)
+    T.rk_step(dt, 2)
+    assert np.array_equal(S.get_state(), T.get_state())
+    S.close()
+    T.close()
