@@ -98,7 +98,7 @@ hd::LaunchShape shape_of(const hd_solver *s);
 // Entry of the compiled stage kernel of the solver's plan; nullptr if none
 // is compiled.
 // The stage kernel of the solver's plan; k3_role selects the 6D degree-3
-// kernel's variant (0 general, 1 first stage, 2 last stage).
+// kernel's variant (0 general, 1 first stage, 2 late increment).
 const void *stage_entry(const hd_solver *s, int k3_role = 0);
 
 // Enqueue the five fused stages of one RK step of s on st, starting from

@@ -289,8 +289,12 @@ hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, in
   if ((uint64_t)ls.grid * ls.block >= (uint64_t(1) << 32))
     return fail(HD_ERR_UNSUPPORTED, "stage launch exceeds 2^32 work-items; use a plan with more "
                                     "nodes per thread");
-  // The first stage reads no increment, the last writes none.
-  const int k3_role = mode == 1 && !prm.read_du ? 1 : (mode == 1 && !prm.write_du ? 2 : 0);
+  // Variants of the 6D degree-3 kernel: the first stage reads no increment;
+  // the late-increment variant serves the last stage (FP64) or every later
+  // stage (FP32), where it measured faster than holding the increment
+  // through the sweeps.
+  const bool f32 = s->prec == HD_FP32;
+  const int k3_role = mode != 1 ? 0 : (!prm.read_du ? 1 : (f32 || !prm.write_du ? 2 : 0));
   const void *fn = hd::rt::stage_entry(s, k3_role);
   if (!fn) return fail(HD_ERR_HIP, "no compiled stage kernel for this plan");
   if (s->field_kind == 2) {

@@ -130,8 +130,8 @@ const void *stage_d6_f32(int n, int rd, int lds, int sd, int opt, int ld);
 
 // Specialised kernel for d = 6 (3 x + 3 v), degree 3: one cell per
 // 256-thread workgroup (stage_k3.hip); options as in hd_plan.
-// role: 0 general (operator application, middle stages), 1 first stage
-// (read_du == 0), 2 last stage (write_du == 0)
+// role: 0 general (operator application, any stage), 1 first stage
+// (read_du == 0), 2 late increment (any stage after the first)
 const void *stage_k3_f64(int options, int role = 0);
 const void *stage_k3_f32(int options, int role = 0);
 

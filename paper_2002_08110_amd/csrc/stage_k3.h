@@ -57,15 +57,16 @@ __device__ __forceinline__ int k3_face_node0(int p, int j) {
 }
 
 // Stage roles, each compiled separately: the general kernel (operator
-// application and the middle stages), the first stage (no increment to read:
-// its registers are free) and the last stage (the increment is loaded only
-// for the update, as nothing overlaps it there anyway).
+// application and stages; the increment loads overlap the sweeps), the
+// first stage (no increment to read: its registers are free) and the
+// late-increment kernel (the increment is loaded only for the update, which
+// frees its registers during the sweeps; any stage after the first).
 constexpr int kK3General = 0, kK3First = 1, kK3Last = 2;
 
 // Register budget per thread. The general FP64 kernel holds the increment
 // through the sweeps and runs 3 workgroups per CU = 3 waves per SIMD (at most
-// 168 VGPRs; 4 would spill); without that, the first and last stages fit 128
-// VGPRs and run 4. FP32: 4.
+// 168 VGPRs; 4 would spill); without that, the first-stage and
+// late-increment variants fit 128 VGPRs and run 4. FP32: 4 (5 would spill).
 template <typename P, int ROLE>
 constexpr int k3_waves_per_eu() {
   return sizeof(P) == 8 ? (ROLE == kK3General ? 3 : 4) : 4;
