@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--precisions", default="fp64,fp32")
     ap.add_argument("--plan", default="", help="override plan, e.g. lds=1,reg_dims=1")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the library's default plan instead of timing the candidates "
+                         "on the workload's mesh (profiled runs: no tuning launches)")
     ap.add_argument("--mode", default="bench",
                     choices=["bench", "stages", "copy", "batch", "serve", "vp", "gauss", "mapped"],
                     help="stages: only run --steps x 5 stage launches per precision (for "
@@ -122,7 +125,7 @@ def run_copy(mib):
 
 
 def measure(case, precision, steps, warmup, plan_override, quadrature="gauss_lobatto",
-            map_eps=0.0):
+            map_eps=0.0, tune=True):
     import torch
 
     from paper_2002_08110_amd.solver import Solver
@@ -145,9 +148,11 @@ def measure(case, precision, steps, warmup, plan_override, quadrature="gauss_lob
     if plan_override:
         S.set_plan(**plan_override)
         plan_source = "override"
-    elif quadrature == "gauss_lobatto" and not map_eps:
+    elif quadrature == "gauss_lobatto" and not map_eps and tune:
         S.tune_plan(dt)
         plan_source = "tuned on this mesh"
+    elif quadrature == "gauss_lobatto" and not map_eps:
+        plan_source = "library default"
     else:
         plan_source = "none"
     torch.cuda.synchronize()
@@ -438,10 +443,10 @@ def run_mapped(case, steps, warmup, precisions, eps):
     print(json.dumps(out), flush=True)
 
 
-def profiled_kernel(precision, plan_override):
-    """The committed counter profile of the default plan's stage kernel
-    (bytes per launch, VALU activity), or None if the kernel source changed
-    since it was taken."""
+def profiled_kernel(precision, plan_override, plan):
+    """The committed counter profile of the stage kernels (bytes per launch,
+    VALU activity), or None if the kernel source changed since it was taken
+    or the profiled run used another plan than `plan`."""
     if plan_override:
         return None
     from paper_2002_08110_amd import profiling
@@ -452,11 +457,25 @@ def profiled_kernel(precision, plan_override):
         data = json.load(f)
     if data.get("kernel_source_digest") != profiling.kernel_source_digest():
         return None
+    # The fields that decide the 6D degree-3 kernel's launch (it ignores the
+    # generic kernel's).
+    keys = ("kernel", "options", "xcd_remap")
+    prof_plan = data.get("plans", {}).get(precision)
+    if not prof_plan or any(prof_plan.get(k) != plan.get(k) for k in keys):
+        return None
+    # The stage launches of one precision use up to three variants (first,
+    # general, late-increment stage); their launch-weighted mean is the
+    # traffic per stage launch.
     want = "stage_k3_kernel<double" if precision == "fp64" else "stage_k3_kernel<float"
-    for name, d in data["kernels"].items():
-        if want in name:
-            return d
-    return None
+    ks = [d for name, d in data["kernels"].items() if want in name]
+    if not ks:
+        return None
+    n = sum(d["launches"] for d in ks)
+    out = {"launches": n, "variants": len(ks),
+           "bytes_per_launch": sum(d["launches"] * d["bytes_per_launch"] for d in ks) / n}
+    if all("valu_busy_pct" in d for d in ks):
+        out["valu_busy_pct"] = sum(d["launches"] * d["valu_busy_pct"] for d in ks) / n
+    return out
 
 
 def cpu_baseline(case, seconds):
@@ -529,14 +548,15 @@ def main():
         return
     results = {}
     for prec in args.precisions.split(","):
-        results[prec] = measure(case, prec, args.steps, args.warmup, plan)
+        results[prec] = measure(case, prec, args.steps, args.warmup, plan, tune=not args.no_tune)
         print("# %s: %.1f GDoF/s per stage, stage kernels %.0f GB/s, stages ms %s, plan %s"
               % (prec, results[prec]["dof_updates_per_s"] / 1e9,
                  results[prec]["stage_kernel_GBps"], results[prec]["stage_ms"],
                  results[prec]["plan"]), file=sys.stderr, flush=True)
     head = results.get("fp64") or next(iter(results.values()))
     achieved = head["stage_kernel_GBps"]
-    prof = profiled_kernel(head["precision"], plan) if args.config == "6d" else None
+    prof = (profiled_kernel(head["precision"], plan, head["plan"]) if args.config == "6d"
+            else None)
     line = {
         "metric": "6D k=3 DoF-updates/s per RK stage, FP64 vs FP32, % HBM peak; p99 latency",
         "value": head["dof_updates_per_s"],

@@ -175,6 +175,13 @@ hd_plan default_plan(const hd_solver *s) {
   // (the autotuner picked streaming for most (d, k) at 1.5e8 DoFs).
   if (p.kernel == 1) p.options = s->prec == HD_FP32 ? 3 : 1;
   else p.options = s->ndofs >= (int64_t(1) << 25) ? 1 : 0;
+  // Cell order of the 6D degree-3 kernel (measured on MI355X over 4^6 to
+  // 9^6 and mixed meshes, with data of full entropy): in FP64 from about
+  // 1e5 cells on, handing consecutive cells to the XCDs in turn keeps all of
+  // them inside one window whose neighbour layers the shared last-level
+  // cache still holds (8^6: 10% faster than contiguous slabs per XCD);
+  // smaller meshes and the FP32 mode run faster with the slabs.
+  if (p.kernel == 1 && s->prec == HD_FP64 && s->ncells >= 100000) p.xcd_remap = 0;
   return p;
 }
 

@@ -14,11 +14,13 @@ Usage:
 """
 from __future__ import annotations
 
+import ast
 import collections
 import csv
 import hashlib
 import json
 import os
+import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -49,6 +51,18 @@ def _pick(means, needle):
     return out
 
 
+def _plans(run_dir):
+    """The launch plan per precision that the counted run printed."""
+    plans = {}
+    log = os.path.join(run_dir, "fetch.log")
+    if os.path.exists(log):
+        for line in open(log):
+            m = re.match(r"# ran \d+ stage launches \((fp\d\d), plan (\{.*\})\)", line)
+            if m:
+                plans[m.group(1)] = ast.literal_eval(m.group(2))
+    return plans
+
+
 def counters(run_dir, copy_mib, out_json, out_md):
     """run_dir holds fetch/, write/, cfetch/, cwrite/ rocprofv3 csv outputs."""
     def csvp(name):
@@ -65,7 +79,8 @@ def counters(run_dir, copy_mib, out_json, out_md):
     w_scale = copy_kib / cw
     res = {"kernel_source_digest": kernel_source_digest(), "copy_mib": copy_mib,
            "copy_fetch_kib": cf, "copy_write_kib": cw,
-           "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
+           "fetch_scale": f_scale, "write_scale": w_scale, "plans": _plans(run_dir),
+           "kernels": {}}
     valu = {}
     if os.path.exists(csvp("valu")):
         valu, _ = _counter_means(csvp("valu"))
@@ -130,6 +145,19 @@ def trace(stats_csv, command, out_md):
         lines.append("| `%s` | %s | %.4f | %.4f | %.4f | %.2f |" % (
             r["Name"][:90], r["Calls"], float(r["AverageNs"]) / 1e6, float(r["MinNs"]) / 1e6,
             float(r["MaxNs"]) / 1e6, float(r["Percentage"])))
+    # The stage launches of one precision run up to three kernel variants
+    # (first stage, general, late increment): their launch-weighted mean is
+    # the average stage launch.
+    mean = []
+    for prec, needle in (("FP64", "stage_k3_kernel<double"), ("FP32 mode", "stage_k3_kernel<float")):
+        rs = [r for r in rows if needle in r["Name"]]
+        if rs:
+            calls = sum(int(r["Calls"]) for r in rs)
+            avg = sum(int(r["Calls"]) * float(r["AverageNs"]) for r in rs) / calls / 1e6
+            mean.append("| %s | %d | %d | %.4f |" % (prec, len(rs), calls, avg))
+    if mean:
+        lines += ["", "Mean stage launch of the 6D degree-3 kernel, weighted by calls:", "",
+                  "| mode | variants | calls | average ms |", "|---|---|---|---|"] + mean
     vp = hashlib.sha256(open(os.path.join(HERE, "csrc/hd_vp.hip"), "rb").read()).hexdigest()[:16]
     lines += ["", "Kernel source digest: `%s` (stage kernels), `%s` (Vlasov-Poisson field)."
               % (kernel_source_digest(), vp)]
