@@ -91,6 +91,12 @@ inline bool k3_eligible(const hd_solver *s) {
   return s->d == 6 && s->dx == 3 && s->n == 4 && s->ndofs < (int64_t(1) << 31);
 }
 
+// Gauss-Legendre quadrature on Cartesian cells runs in the 6D degree-3
+// layout when the plan selects that kernel (kernel 0: the sweep kernel).
+inline bool k3g_used(const hd_solver *s) {
+  return s->quad == 1 && !s->mapped() && s->plan.kernel == 1 && k3_eligible(s);
+}
+
 // Grid, workgroup size and dynamic LDS of one stage launch under the
 // solver's plan.
 hd::LaunchShape shape_of(const hd_solver *s);

@@ -16,6 +16,7 @@
 
 #include "hd_internal.h"
 #include "stage_gauss.h"
+#include "stage_k3_gauss.h"
 #include "stage_dispatch.h"
 #include "stage_k3.h"
 
@@ -189,6 +190,12 @@ hd_plan default_plan(const hd_solver *s) {
 
 hd::LaunchShape hd::rt::shape_of(const hd_solver *s) {
   hd::LaunchShape ls{};
+  if (hd::rt::k3g_used(s)) {
+    ls.grid = (unsigned)s->ncells;
+    ls.block = 256;
+    ls.shmem = s->prec == HD_FP32 ? hd::k3g_lds_bytes<float>() : hd::k3g_lds_bytes<double>();
+    return ls;
+  }
   if (s->quad == 1 || s->mapped()) {
     ls.grid = (unsigned)s->ncells;
     ls.block = (unsigned)hd::gauss_threads((int)s->nd);
@@ -225,6 +232,7 @@ namespace rt {
 
 const void *stage_entry(const hd_solver *s, int k3_role) {
   const bool f32 = s->prec == HD_FP32;
+  if (k3g_used(s)) return hd::stage_k3g_entry(f32);
   if (s->quad == 1 || s->mapped()) return hd::stage_gauss_entry(s->d, s->n, f32, s->mapped());
   if (s->plan.kernel == 1) return f32 ? hd::stage_k3_f32(s->plan.options, k3_role)
                                       : hd::stage_k3_f64(s->plan.options, k3_role);
@@ -269,13 +277,46 @@ hipError_t allow_large_lds(const void *fn) {
   return e;
 }
 
+// The nodal-space matrices of the Gauss-Legendre form at degree 3 (host,
+// FP64): Dt = B^-1 Dg B, G = B^-1 diag(g) B, B^-1 lift_s.
+template <typename P>
+void k3g_tables(const hd::GaussTables1D &g, hd::K3GaussTables<P> *kt) {
+  double Dt[16], G[16];
+  for (int i = 0; i < 4; ++i)
+    for (int m = 0; m < 4; ++m) {
+      double dt = 0.0, gg = 0.0;
+      for (int q = 0; q < 4; ++q) {
+        double dgb = 0.0;
+        for (int r = 0; r < 4; ++r) dgb += g.Dg[q * 4 + r] * g.B[r * 4 + m];
+        dt += g.Binv[i * 4 + q] * dgb;
+        gg += g.Binv[i * 4 + q] * g.g[q] * g.B[q * 4 + m];
+      }
+      Dt[i * 4 + m] = dt;
+      G[i * 4 + m] = gg;
+    }
+  for (int q = 0; q < 16; ++q) {
+    kt->B[q] = (P)g.B[q];
+    kt->Binv[q] = (P)g.Binv[q];
+    kt->Dt[q] = (P)Dt[q];
+    kt->G[q] = (P)G[q];
+  }
+  for (int sd = 0; sd < 2; ++sd)
+    for (int i = 0; i < 4; ++i) {
+      double b = 0.0;
+      for (int q = 0; q < 4; ++q) b += g.Binv[i * 4 + q] * g.lift[sd][q];
+      kt->Blift[sd][i] = (P)b;
+    }
+  for (int q = 0; q < 4; ++q) kt->g[q] = (P)g.g[q];
+}
+
 template <typename P>
 hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, int mode,
                     int stage, double dt, hipStream_t st) {
   hd::StageParams<P> prm;
   // The sweep kernel (Gauss-Legendre quadrature or mapped cells) reads the
   // fields in their own form, not the specialised kernel's.
-  const bool sweep = s->quad == 1 || s->mapped();
+  const bool k3g = hd::rt::k3g_used(s);
+  const bool sweep = (s->quad == 1 || s->mapped()) && !k3g;
   fill_params<P>(s, &prm, sweep ? 0 : s->plan.kernel);
   const hd::LaunchShape ls = hd::rt::shape_of(s);
   prm.nblocks = ls.grid;
@@ -321,8 +362,10 @@ hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, in
       return fail(HD_ERR_HIP, std::string("raising the LDS limit: ") + hipGetErrorString(ae));
   }
   hd::GaussTables<P> gt;
-  void *args[] = {&prm, &gt};
-  if (s->quad == 1 || s->mapped()) {
+  hd::K3GaussTables<P> kt;
+  void *args[] = {&prm, k3g ? (void *)&kt : (void *)&gt};
+  if (k3g) k3g_tables(s->gtab, &kt);
+  else if (s->quad == 1 || s->mapped()) {
     const hd::GaussTables1D &src = s->quad == 1 ? s->gtab : s->gltab;
     const int n = s->n;
     for (int q = 0; q < n * n; ++q) {

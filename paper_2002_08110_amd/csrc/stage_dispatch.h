@@ -135,6 +135,11 @@ const void *stage_d6_f32(int n, int rd, int lds, int sd, int opt, int ld);
 const void *stage_k3_f64(int options, int role = 0);
 const void *stage_k3_f32(int options, int role = 0);
 
+// Gauss-Legendre quadrature for d = 6 (3 x + 3 v), degree 3, Cartesian
+// cells, in the thread layout of the collocation kernel above
+// (stage_k3_gauss.hip); streaming stores.
+const void *stage_k3g_entry(bool f32);
+
 // Sweep kernel (stage_gauss.hip): Gauss-Legendre quadrature on Cartesian
 // cells, or either quadrature on mapped cells; one cell per workgroup;
 // nullptr where the cell's LDS does not fit.
