@@ -226,11 +226,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
       load_layers(side);
       __syncthreads();  // the first pass's layers are consumed
     }
-    // Nodal jump own - neighbour on the face layer, face node p = t + 256 q.
-    P J[6][4];
+    // Per dimension: the nodal jump own - neighbour on the face layer (face
+    // node p = t + 256 q). x-dimensions: to LDS, weighted along v_j below.
+    // v-dimensions: x-transform, upwind weight at the x-Gauss point, inverse
+    // transform; dims 5 and 6 lift in registers, dim 4 via LDS.
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
       if (side[j] < 0) continue;
+      P f[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int node0 = k3_face_node0(t + 256 * q, j);
@@ -238,17 +241,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
         if (j == 4) own = side[j] ? u[3 + 4 * q] : u[4 * q];
         else if (j == 5) own = side[j] ? u[q + 12] : u[q];
         else own = cellb[side[j] ? node0 + 3 * (1 << (2 * j)) : node0];
-        J[j][q] = own - to_p<P>(fv[j][q]);
+        f[q] = own - to_p<P>(fv[j][q]);
       }
-    }
-    // v-dimension faces: x-transform, upwind weight at the x-Gauss point,
-    // inverse transform; dims 5 and 6 lift in registers, dim 4 via LDS.
+      if (j < 3) {
 #pragma unroll
-    for (int j = 3; j < 6; ++j) {
-      if (side[j] < 0) continue;
-      P f[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) f[q] = J[j][q];
+        for (int q = 0; q < 4; ++q) faceb[j * F + t + 256 * q] = f[q];
+        continue;
+      }
       k3g_x3<4>(tB, f, l);
       const P a = side[j] ? eg[j - 3] : -eg[j - 3];
       const P m = a < P(0) ? a : P(0);
@@ -273,13 +272,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
           for (int i6 = 0; i6 < 4; ++i6) acc[q + 4 * i6] += ih * bl[i6] * f[q];
       }
-    }
-    // x-dimension faces: the jump to LDS, weighted along v_j below
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      if (side[j] < 0) continue;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) faceb[j * F + t + 256 * q] = J[j][q];
     }
     __syncthreads();
     // dim 4 face: lift along the waves
@@ -399,68 +391,58 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
     for (int s = 0; s < 16; ++s) acc[s] -= ih * y[s];
   }
+  const int off3 = (l & 15) + 64 * w;  // the lane's line along i3 in the cell
   {
-    // j = 2: G along i6 (registers), Dt along i3
+    // j = 2: Dt along i3 (lanes 16 apart, from LDS), then G along i6
+    const P r0 = tDt[i3 * 4], r1 = tDt[i3 * 4 + 1], r2 = tDt[i3 * 4 + 2], r3 = tDt[i3 * 4 + 3];
     P y[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s)
+      y[s] = r0 * cellb[off3 + 256 * s] + r1 * cellb[off3 + 16 + 256 * s] +
+             r2 * cellb[off3 + 32 + 256 * s] + r3 * cellb[off3 + 48 + 256 * s];
+    const P ih = prm.inv_h[2];
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       const int i6 = s >> 2, s0 = s & 3;
       P g6 = P(0);
 #pragma unroll
-      for (int mm = 0; mm < 4; ++mm) g6 += gt.G[i6 * 4 + mm] * u[s0 + 4 * mm];
-      y[s] = alpha[2] * u[s] + vhh[2] * g6;
+      for (int mm = 0; mm < 4; ++mm) g6 += gt.G[i6 * 4 + mm] * y[s0 + 4 * mm];
+      acc[s] -= ih * (alpha[2] * y[s] + vhh[2] * g6);
     }
-    k3g_lane<3, 16>(tDt, y, l);
-    const P ih = prm.inv_h[2];
-#pragma unroll
-    for (int s = 0; s < 16; ++s) acc[s] -= ih * y[s];
   }
-  // ---- volume, v-dimensions: B^-1(x3) [sum_j E_j(g) (B(x3) Dt_{v_j} u) / h_j] ----
+  // ---- volume, v-dimensions ----
+  // B^-1(x3) [sum_j E_j(g) (Dt along v_j) Ux / h_j], Ux = B(x3) u: the
+  // derivatives along v_j commute with the x-transform, which is applied once.
   {
+    P ux[16];
+    {
+      const P r0 = tB[i3 * 4], r1 = tB[i3 * 4 + 1], r2 = tB[i3 * 4 + 2], r3 = tB[i3 * 4 + 3];
+#pragma unroll
+      for (int s = 0; s < 16; ++s)
+        ux[s] = r0 * cellb[off3 + 256 * s] + r1 * cellb[off3 + 16 + 256 * s] +
+                r2 * cellb[off3 + 32 + 256 * s] + r3 * cellb[off3 + 48 + 256 * s];
+    }
+    k3g_lane<1, 16>(tB, ux, l);
+    k3g_lane<2, 16>(tB, ux, l);
+    // Ux to LDS for the derivative across the waves (the face layers are
+    // consumed: every wave passed the barrier below only after its reads)
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 16; ++s) faceb[t + 256 * s] = ux[s];
+    __syncthreads();
+    const P c4 = prm.inv_h[3] * eg[0], c5 = prm.inv_h[4] * eg[1], c6 = prm.inv_h[5] * eg[2];
     P z[16];
-    {
-      P y[16];
 #pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        P d4 = P(0);
+    for (int s = 0; s < 16; ++s) {
+      const int i5 = s & 3, i6 = s >> 2;
+      P d4 = P(0), d5 = P(0), d6 = P(0);
 #pragma unroll
-        for (int mm = 0; mm < 4; ++mm) d4 += tDt[w * 4 + mm] * cellb[l + 64 * mm + 256 * s];
-        y[s] = d4;
+      for (int mm = 0; mm < 4; ++mm) {
+        d4 += tDt[w * 4 + mm] * faceb[l + 64 * mm + 256 * s];
+        d5 += gt.Dt[i5 * 4 + mm] * ux[4 * i6 + mm];
+        d6 += gt.Dt[i6 * 4 + mm] * ux[i5 + 4 * mm];
       }
-      k3g_x3<16>(tB, y, l);
-      const P c4 = prm.inv_h[3] * eg[0];
-#pragma unroll
-      for (int s = 0; s < 16; ++s) z[s] = c4 * y[s];
-    }
-    {
-      P y[16];
-#pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        const int i5 = s & 3, s0 = s - i5;
-        P d5 = P(0);
-#pragma unroll
-        for (int mm = 0; mm < 4; ++mm) d5 += gt.Dt[i5 * 4 + mm] * u[s0 + mm];
-        y[s] = d5;
-      }
-      k3g_x3<16>(tB, y, l);
-      const P c5 = prm.inv_h[4] * eg[1];
-#pragma unroll
-      for (int s = 0; s < 16; ++s) z[s] += c5 * y[s];
-    }
-    {
-      P y[16];
-#pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        const int i6 = s >> 2, s0 = s & 3;
-        P d6 = P(0);
-#pragma unroll
-        for (int mm = 0; mm < 4; ++mm) d6 += gt.Dt[i6 * 4 + mm] * u[s0 + 4 * mm];
-        y[s] = d6;
-      }
-      k3g_x3<16>(tB, y, l);
-      const P c6 = prm.inv_h[5] * eg[2];
-#pragma unroll
-      for (int s = 0; s < 16; ++s) z[s] += c6 * y[s];
+      z[s] = c4 * d4 + c5 * d5 + c6 * d6;
     }
     k3g_lane<3, 16>(tBinv, z, l);
     k3g_lane<2, 16>(tBinv, z, l);
