@@ -33,17 +33,22 @@ constexpr size_t k3_lds_bytes() {
 }
 static_assert(4 * kK3Face == kK3Nodes, "face layers and cell share the LDS");
 
+// Cross-lane moves with every row and bank enabled: each lane reads a
+// valid source lane under the patterns used here (quad permutations, row
+// rotations), so no lane keeps a previous value and none is supplied (which
+// spares a register initialisation per move and lets FP32 arithmetic take
+// the pattern as an operand modifier).
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double x) {
   const long long v = __builtin_bit_cast(long long, x);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffll), CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(v & 0xffffffffll), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(v >> 32), CTRL, 0xf, 0xf, false);
   return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
 }
 template <int CTRL>
 __device__ __forceinline__ float dpp_move(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL,
-                                                               0xf, 0xf, false));
+  return __builtin_bit_cast(float,
+                            __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xf, 0xf, false));
 }
 // quad_perm [m, m, m, m]: every lane reads lane m of its group of four.
 constexpr int quad_bcast(int m) { return m | (m << 2) | (m << 4) | (m << 6); }
