@@ -91,8 +91,10 @@ __device__ __forceinline__ void k3g_x3(const P *M, P (&v)[NV], int l) {
   k3g_lane<3, NV>(M, v, l);
 }
 
+// FP64: 2 waves per SIMD (256 VGPRs); FP32: 3 (168 VGPRs, a few values spilled,
+// measured faster than 2 waves without spills).
 template <typename P, int OPT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(P) == 8 ? 2 : 3, sizeof(P) == 8 ? 2 : 3)))
     stage_k3g_kernel(const StageParams<P> prm, const K3GaussTables<P> gt) {
   constexpr bool NT = (OPT & kOptStream) != 0;
   constexpr int ND = kK3Nodes, F = kK3Face;

@@ -115,7 +115,8 @@ def test_rk_steps_match_oracle(precision, d, k, cells):
     S.close()
 
 
-@pytest.mark.parametrize("dx,cells,k", [(1, [6, 4], 3), (2, [3, 2, 2, 3], 2), (3, [2, 1, 2, 1, 2, 1], 2)])
+@pytest.mark.parametrize("dx,cells,k", [(1, [6, 4], 3), (2, [3, 2, 2, 3], 2), (3, [2, 1, 2, 1, 2, 1], 2),
+                                       (3, [2, 1, 1, 1, 2, 1], 3)])
 def test_vlasov_poisson_with_gauss_quadrature(dx, cells, k):
     lo = [0.0] * dx + [-5.0] * dx
     hi = [2 * np.pi] * dx + [4.0] * dx
@@ -173,9 +174,12 @@ def test_batch_mixing_quadratures_and_mapped_cells_equals_alone():
     cases = [W.phase_space_case("p", 2, 2, [3, 2, 2, 3], 3, 3),
              W.phase_space_case("q", 3, 3, [2, 1, 1, 1, 2, 1], 2, 3),
              W.phase_space_case("r", 1, 1, [6, 5], 4, 3),
-             W.phase_space_case("s", 2, 2, [2, 3, 2, 2], 2, 3)]
+             W.phase_space_case("s", 2, 2, [2, 3, 2, 2], 2, 3),
+             W.phase_space_case("t", 3, 3, [1, 2, 1, 1, 2, 1], 3, 3),
+             W.phase_space_case("v", 3, 3, [2, 1, 1, 2, 1, 1], 3, 3)]
     setups = [("gauss_lobatto", 0.0, "fp64"), ("gauss_legendre", 0.0, "fp64"),
-              ("gauss_lobatto", 0.02, "fp64"), ("gauss_legendre", 0.03, "fp32")]
+              ("gauss_lobatto", 0.02, "fp64"), ("gauss_legendre", 0.03, "fp32"),
+              ("gauss_legendre", 0.0, "fp64"), ("gauss_legendre", 0.0, "fp32")]
 
     def make(case, quad, eps, prec):
         S = gpu_solver(case, prec)
