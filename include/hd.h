@@ -82,7 +82,10 @@ typedef struct hd_batch hd_batch;    /* opaque */
  *              registers (1 or 2; at most dim_v).
  *  kernel:     0 = the generic kernel (the fields above apply); 1 = the
  *              kernel specialised for d = 6 (3 x + 3 v) at degree 3, one cell
- *              per 256-thread workgroup (only xcd_remap and options apply).
+ *              per 256-thread workgroup (only xcd_remap and options apply;
+ *              its FP64 first- and last-stage variants always take one slab
+ *              per XCD). Under quadrature 1 it selects the Gauss-Legendre
+ *              kernel of the same layout (see hd_set_quadrature).
  *  options:    bit 0 (both kernels): non-temporal (streaming) loads and
  *              stores of the stage increment du and stores of the output
  *              solution, so they do not displace cached neighbour data;
@@ -181,7 +184,11 @@ hd_status hd_get_field(hd_solver *s, double *E_host, hd_stream stream);
  * the E table). The nodal GL basis and the state layout are the same for
  * both. Quadrature 1 runs one cell per workgroup with two cell-sized arrays
  * and a face layer in LDS and returns HD_ERR_UNSUPPORTED where those exceed
- * 160 KiB (FP64 6D degree >= 4, FP32 6D degree 5). Launch plans apply to
+ * 160 KiB (FP64 6D degree >= 4, FP32 6D degree 5). For d = 6 (3 x + 3 v) at
+ * degree 3 on Cartesian cells, plan kernel 1 (the default) selects a second
+ * Gauss-Legendre kernel in the specialised kernel's thread layout (the same
+ * operator, evaluated with 4 x 4 matrices in nodal space; xcd_remap
+ * applies) and kernel 0 the general one; the other plan fields apply to
  * quadrature 0 only. */
 hd_status hd_set_quadrature(hd_solver *s, int quadrature);
 
