@@ -199,7 +199,7 @@ hd::LaunchShape hd::rt::shape_of(const hd_solver *s) {
   if (s->quad == 1 || s->mapped()) {
     ls.grid = (unsigned)s->ncells;
     ls.block = (unsigned)hd::gauss_threads((int)s->nd);
-    ls.shmem = (size_t)hd::gauss_lds_elems(s->d, s->n, s->dx, s->mapped()) * s->psize();
+    ls.shmem = (size_t)hd::gauss_lds_elems(s->d, s->n, s->dx, s->mapped(), (int)s->psize()) * s->psize();
     return ls;
   }
   if (s->plan.kernel == 1) {
@@ -930,8 +930,8 @@ hd_status hd_set_mapping(hd_solver *s, double eps) {
     return fail(HD_ERR_UNSUPPORTED, "the Vlasov-Poisson field needs Cartesian cells");
   if (eps != 0.0 && !hd::stage_gauss_entry(s->d, s->n, s->prec == HD_FP32, true))
     return fail(HD_ERR_UNSUPPORTED,
-                "the mapped-cell kernel holds two cell-sized arrays, a face layer and the "
-                "x-metric in LDS: this (d, degree, precision) exceeds 160 KiB");
+                "the mapped-cell kernel holds two cell-sized arrays and a face layer in LDS: "
+                "this (d, degree, precision) exceeds 160 KiB or is not compiled");
   const double old = s->map_eps;
   s->map_eps = eps;
   changed(s);

@@ -61,11 +61,21 @@ template <int N>
 __host__ __device__ constexpr int gauss_pad(int q) { return q + q / (N * N); }
 constexpr int gauss_padded(int n, int count) { return count + count / (n * n) + 1; }
 
+// Where mapped cells read their metric: FP32 stages it in LDS; FP64 reads it
+// from global memory (a few KiB per x-cell, shared by every velocity cell,
+// so cache hits), because in LDS it would cost the FP64 6D degree-3 kernel
+// its second workgroup per CU (measured: 103 against 58 ms per stage),
+// while FP32 is held to 3 waves per SIMD by registers and loses 10% on the
+// global reads.
+constexpr bool gauss_metric_in_lds(int psize) { return psize == 4; }
+
 // LDS elements of P: U and the accumulator Y (n^d each), one face layer,
-// E at the x-Gauss points, the 1D tables and, for mapped cells, the metric.
-constexpr int gauss_lds_elems(int d, int n, int dx, bool mapped = false) {
+// E at the x-Gauss points, the 1D tables and, for mapped cells in FP32, the
+// metric.
+constexpr int gauss_lds_elems(int d, int n, int dx, bool mapped, int psize) {
   return 2 * gauss_padded(n, ipow(n, d)) + gauss_padded(n, ipow(n, d - 1)) + ipow(n, dx) * dx +
-         gauss_table_elems(n) + (mapped ? gauss_metric_elems(n, dx) : 0);
+         gauss_table_elems(n) +
+         (mapped && gauss_metric_in_lds(psize) ? gauss_metric_elems(n, dx) : 0);
 }
 
 // In place along one axis (stride = N^axis) of an N-ary array of `total`
@@ -168,8 +178,6 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
   P *tB = EG + NXN * DX, *tBinv = tB + N * N, *tDg = tBinv + N * N;
   P *tExt = tDg + N * N, *tLift = tExt + 2 * N, *tG = tLift + 2 * N, *tOm = tG + N;
   constexpr int MXE = DX * DX + 1, NFX = NXN / N;
-  P *MX = tOm + N;                 // [xq][MXE] (mapped cells)
-  P *MF = MX + NXN * MXE;          // [j][side][face x-point][DX]
   const int t = threadIdx.x;
   if (t == 0) {
 #pragma unroll
@@ -210,9 +218,18 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
     xs *= prm.cells[m];
   }
   P detv = P(1);
+  // mapped cells: this x-cell's metric, [xq][MXE] then [j][side][face
+  // x-point][DX], read from LDS (FP32) or global memory (FP64)
+  constexpr bool ML = gauss_metric_in_lds(sizeof(P));
+  const double *MXg = MAPPED ? prm.xmetric + (uint64_t)xcell * gauss_metric_elems(N, DX) : nullptr;
+  P *MXl = tOm + N;
+  auto metric = [&](int i) -> P {
+    if constexpr (ML) return MXl[i];
+    else return (P)MXg[i];
+  };
   if constexpr (MAPPED) {
-    const double *mt = prm.xmetric + (uint64_t)xcell * gauss_metric_elems(N, DX);
-    for (int i = t; i < gauss_metric_elems(N, DX); i += T) MX[i] = (P)mt[i];
+    if constexpr (ML)
+      for (int i = t; i < gauss_metric_elems(N, DX); i += T) MXl[i] = (P)MXg[i];
 #pragma unroll
     for (int m = DX; m < D; ++m) detv *= prm.vh[m];
   }
@@ -249,14 +266,14 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
   };
   // ahat_j at the cell point q (mapped cells)
   auto ahat_at = [&](int j, int q) -> P {
-    const P *mx = MX + (q % NXN) * MXE;
+    const int mx = (q % NXN) * MXE;
     if (j < DX) {
       P s = P(0);
 #pragma unroll
-      for (int k2 = 0; k2 < DX; ++k2) s += mx[j * DX + k2] * a_at(k2, q);
+      for (int k2 = 0; k2 < DX; ++k2) s += metric(mx + j * DX + k2) * a_at(k2, q);
       return detv * s;
     }
-    return mx[DX * DX] * detv * prm.inv_h[j] * a_at(j, q);
+    return metric(mx + DX * DX) * detv * prm.inv_h[j] * a_at(j, q);
   };
   // ahat_j at the point with index q (digit j ignored) on face `side` of
   // dimension j
@@ -264,10 +281,10 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
     if (j < DX) {
       const int sj = ipow(N, j), xq = q % NXN;
       const int xp = xq % sj + (xq / (sj * N)) * sj;
-      const P *mf = MF + ((j * 2 + side) * NFX + xp) * DX;
+      const int mf = NXN * MXE + ((j * 2 + side) * NFX + xp) * DX;
       P s = P(0);
 #pragma unroll
-      for (int k2 = 0; k2 < DX; ++k2) s += mf[k2] * a_at(k2, q);
+      for (int k2 = 0; k2 < DX; ++k2) s += metric(mf + k2) * a_at(k2, q);
       return detv * s;
     }
     return ahat_at(j, q);
@@ -393,7 +410,7 @@ __global__ void __launch_bounds__(gauss_threads(ipow(N, D)))
       }
     }
     // inverse of |J|
-    for (int q = t; q < ND; q += T) Yb[gauss_pad<N>(q)] /= MX[(q % NXN) * MXE + DX * DX] * detv;
+    for (int q = t; q < ND; q += T) Yb[gauss_pad<N>(q)] /= metric((q % NXN) * MXE + DX * DX) * detv;
     __syncthreads();
   } else {
     // Per dimension j: the faces' scaled upwind jumps at their Gauss points,

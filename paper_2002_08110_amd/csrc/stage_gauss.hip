@@ -14,7 +14,7 @@ namespace {
 // with an instruction-selection error.
 template <int D, int N, int DX, typename P, bool M>
 constexpr bool gauss_compiled() {
-  return (size_t)gauss_lds_elems(D, N, DX, M) * sizeof(P) + 1024 <= kMaxLdsBytes &&
+  return (size_t)gauss_lds_elems(D, N, DX, M, (int)sizeof(P)) * sizeof(P) + 1024 <= kMaxLdsBytes &&
          !(M && D == 5 && N == 6);
 }
 

@@ -66,8 +66,9 @@ def lds_ok(d, k, precision):
 
     def padded(c):
         return c + c // (n * n) + 1
-    metric = n ** dx * (dx * dx + 1) + dx * 2 * n ** (dx - 1) * dx
-    lds = (2 * padded(n ** d) + padded(n ** (d - 1)) + n ** dx * dx + 3 * n * n + 6 * n + metric)
+    lds = 2 * padded(n ** d) + padded(n ** (d - 1)) + n ** dx * dx + 3 * n * n + 6 * n
+    if precision == "fp32":  # the metric is staged in LDS in FP32 only
+        lds += n ** dx * (dx * dx + 1) + dx * 2 * n ** (dx - 1) * dx
     return lds * (8 if precision == "fp64" else 4) + 1024 <= 160 * 1024 and not (d == 5 and k == 5)
 
 
