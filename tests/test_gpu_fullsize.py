@@ -50,3 +50,64 @@ def test_headline_operator_and_stage_sampled(precision):
     want = u_host[idx].reshape(len(cells), nd) + B[0] * (dt * ref)
     assert rel_l2(u1 - u_host[idx].reshape(len(cells), nd),
                   want - u_host[idx].reshape(len(cells), nd)) <= tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_headline_full_step_stage_by_stage_sampled(precision):
+    # The five stages of one step at the headline size, launched as the
+    # benchmark launches them (first-stage, general and last-stage kernel
+    # variants). The increment is local to a cell, so the sampled cells'
+    # du and u can be followed exactly: after each stage the oracle
+    # evaluates L(u_s) on the samples from the full device state.
+    import oracle
+    A, B, _ = oracle.lsrk45_coefficients()
+    case = W.CONFIG_6D
+    nd = (case.degree + 1) ** case.d
+    ncells = int(np.prod(case.cells))
+    S = gpu_solver(case, precision)
+    P = oracle_problem(case)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(2020)
+    u = torch.randn(case.ndofs, dtype=torch.float64, device="cuda", generator=g)
+    S.set_state(u)
+    del u
+    dt = S.stable_dt(case.cfl)
+    cells = _sample_cells(ncells, seed=29, count=12)
+    idx = (cells[:, None] * nd + np.arange(nd)[None, :]).reshape(-1)
+    idx_t = torch.from_numpy(idx).cuda()
+    host = np.empty(case.ndofs)
+    du = np.zeros(len(idx))
+    tol = TOL_FP64 if precision == "fp64" else 5e-6  # FP32 increments, chained
+    for st in range(5):
+        host[:] = S.state_tensor().cpu().numpy()
+        us = host[idx]
+        L = P.apply_cells(host, cells)
+        du = A[st] * du + dt * L
+        S.rk_stage(st, dt)
+        got = S.state_tensor()[idx_t].cpu().numpy()
+        assert rel_l2(got - us, B[st] * du) <= tol, st
+    S.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_headline_gauss_legendre_operator_sampled(precision):
+    # The 6D degree-3 Gauss-Legendre kernel at the headline size.
+    case = W.CONFIG_6D
+    nd = (case.degree + 1) ** case.d
+    ncells = int(np.prod(case.cells))
+    S = gpu_solver(case, precision)
+    S.set_quadrature("gauss_legendre")
+    P = oracle_problem(case)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(77)
+    u = torch.randn(case.ndofs, dtype=torch.float64, device="cuda", generator=g)
+    out = S.apply(u)
+    cells = _sample_cells(ncells, seed=31, count=6)
+    ref = P.apply_cells(u.cpu().numpy(), cells, mode=2).reshape(len(cells), nd)
+    idx = (cells[:, None] * nd + np.arange(nd)[None, :]).reshape(-1)
+    got = out[torch.from_numpy(idx).cuda()].double().cpu().numpy().reshape(len(cells), nd)
+    tol = TOL_FP64 if precision == "fp64" else 5e-6
+    assert rel_l2(got, ref) <= tol
+    if precision == "fp64":
+        assert rel_max(got, ref) <= tol
+    S.close()
