@@ -17,6 +17,7 @@
 #include "hd_internal.h"
 #include "stage_gauss.h"
 #include "stage_k3_gauss.h"
+#include "stage_k3_mapped.h"
 #include "stage_dispatch.h"
 #include "stage_k3.h"
 
@@ -196,6 +197,12 @@ hd::LaunchShape hd::rt::shape_of(const hd_solver *s) {
     ls.shmem = s->prec == HD_FP32 ? hd::k3g_lds_bytes<float>() : hd::k3g_lds_bytes<double>();
     return ls;
   }
+  if (hd::rt::k3m_used(s)) {
+    ls.grid = (unsigned)s->ncells;
+    ls.block = 256;
+    ls.shmem = s->prec == HD_FP32 ? hd::k3m_lds_bytes<float>() : hd::k3m_lds_bytes<double>();
+    return ls;
+  }
   if (s->quad == 1 || s->mapped()) {
     ls.grid = (unsigned)s->ncells;
     ls.block = (unsigned)hd::gauss_threads((int)s->nd);
@@ -233,6 +240,7 @@ namespace rt {
 const void *stage_entry(const hd_solver *s, int k3_role) {
   const bool f32 = s->prec == HD_FP32;
   if (k3g_used(s)) return hd::stage_k3g_entry(f32);
+  if (k3m_used(s)) return hd::stage_k3m_entry(f32);
   if (s->quad == 1 || s->mapped()) return hd::stage_gauss_entry(s->d, s->n, f32, s->mapped());
   if (s->plan.kernel == 1) return f32 ? hd::stage_k3_f32(s->plan.options, k3_role)
                                       : hd::stage_k3_f64(s->plan.options, k3_role);
@@ -315,8 +323,8 @@ hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, in
   hd::StageParams<P> prm;
   // The sweep kernel (Gauss-Legendre quadrature or mapped cells) reads the
   // fields in their own form, not the specialised kernel's.
-  const bool k3g = hd::rt::k3g_used(s);
-  const bool sweep = (s->quad == 1 || s->mapped()) && !k3g;
+  const bool k3g = hd::rt::k3g_used(s), k3m = hd::rt::k3m_used(s);
+  const bool sweep = (s->quad == 1 || s->mapped()) && !k3g && !k3m;
   fill_params<P>(s, &prm, sweep ? 0 : s->plan.kernel);
   const hd::LaunchShape ls = hd::rt::shape_of(s);
   prm.nblocks = ls.grid;
@@ -347,7 +355,7 @@ hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, in
   // and late-increment variants measured faster with one slab per XCD at 8^6
   // on data of full entropy (5.86 against 6.00 ms and 5.50 against 5.55 ms),
   // where the general variant is 3% faster with the window order.
-  if (!k3g && !sweep && s->plan.kernel == 1 && !f32 && k3_role != 0) prm.xcd_remap = 1;
+  if (!k3g && !k3m && !sweep && s->plan.kernel == 1 && !f32 && k3_role != 0) prm.xcd_remap = 1;
   const void *fn = hd::rt::stage_entry(s, k3_role);
   if (!fn) return fail(HD_ERR_HIP, "no compiled stage kernel for this plan");
   if (s->field_kind == 2) {
@@ -368,8 +376,16 @@ hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, in
   }
   hd::GaussTables<P> gt;
   hd::K3GaussTables<P> kt;
-  void *args[] = {&prm, k3g ? (void *)&kt : (void *)&gt};
+  hd::K3MappedTables<P> km;
+  void *args[] = {&prm, k3g ? (void *)&kt : (k3m ? (void *)&km : (void *)&gt)};
   if (k3g) k3g_tables(s->gtab, &kt);
+  if (k3m) {
+    // Dw = W^-1 D^T W of the Gauss-Lobatto collocation
+    for (int q = 0; q < 4; ++q)
+      for (int m = 0; m < 4; ++m) km.Dw[q * 4 + m] = (P)(s->tab.D[m * 4 + q] * s->tab.w[m] / s->tab.w[q]);
+    km.winv = (P)(1.0 / s->tab.w[0]);
+    prm.xmetric = s->xmetric();
+  }
   else if (s->quad == 1 || s->mapped()) {
     const hd::GaussTables1D &src = s->quad == 1 ? s->gtab : s->gltab;
     const int n = s->n;

@@ -173,3 +173,44 @@ def test_invalid_mappings_are_rejected():
     with pytest.raises(HDError):
         U.set_mapping(0.01)
     U.close()
+
+
+@pytest.mark.parametrize("field", ["constant", "sine", "table"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_6d_k3_collocation_layout_and_sweep_kernels_match_the_oracle(field, precision):
+    # Mapped 6D degree 3 with collocation has two kernels: the collocation
+    # kernel's thread layout (plan kernel 1, the default) and the sweep
+    # kernel (kernel 0). Both against the oracle's mapped collocation.
+    case = case_of(6, 3, field)
+    case.cells = [2, 1, 2, 1, 1, 2]
+    E = W.random_field_table(x_table_size(case), seed=13) if field == "table" else None
+    P = oracle_of(case, E)
+    u = W.random_state(P.ndofs, seed=41)
+    ref = P.apply(u, mode=0)
+    outs = []
+    for kernel in (1, 0):
+        S = solver_of(case, precision, "gauss_lobatto", E)
+        S.set_plan(kernel=kernel)
+        out = S.apply(torch.from_numpy(u).cuda()).double().cpu().numpy()
+        tol = TOL_FP64 if precision == "fp64" else 5e-6
+        assert rel_l2(out, ref) <= tol, kernel
+        if precision == "fp64":
+            assert rel_max(out, ref) <= TOL_FP64, kernel
+        outs.append(out)
+        S.close()
+    assert rel_l2(outs[0], outs[1]) <= (1e-13 if precision == "fp64" else 5e-6)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_6d_k3_collocation_rk_steps_on_mapped_cells(precision):
+    case = W.phase_space_case("p", 3, 3, [2, 1, 1, 1, 2, 1], 3, 2)
+    P = oracle_of(case)
+    S = solver_of(case, precision, "gauss_lobatto")
+    assert S.get_plan()["kernel"] == 1
+    u0 = W.random_state(P.ndofs, seed=43)
+    dt = P.stable_dt(case.cfl)
+    ref = P.rk_steps(u0, dt, case.steps, mode=0)
+    S.set_state(u0)
+    S.rk_step(dt, case.steps)
+    assert rel_l2(S.get_state(), ref) <= (TOL_FP64 if precision == "fp64" else 1e-5)
+    S.close()
