@@ -124,10 +124,11 @@ def counters(run_dir, copy_mib, out_json, out_md):
                              "--mode stages --steps 2"),
                             ("cfetch", "FETCH_SIZE", "--mode copy --copy-mib %d" % copy_mib),
                             ("cwrite", "WRITE_SIZE", "--mode copy --copy-mib %d" % copy_mib)):
-        lines.append("rocprofv3 --pmc %s --output-format csv -d gpurun_out/prof/%s -o %s -- "
-                     "python3 bench.py %s" % (cnt, name, name, mode))
-    lines += ["python -m paper_2002_08110_amd.profiling counters gpurun_out/prof %d "
-              "profiles/<name>_traffic.json profiles/<name>_counters.md" % copy_mib, "```"]
+        lines.append("rocprofv3 --pmc %s --output-format csv -d %s/%s -o %s -- "
+                     "python3 bench.py %s" % (cnt, run_dir.rstrip("/"), name, name, mode))
+    lines += ["python -m paper_2002_08110_amd.profiling counters %s %d "
+              "profiles/<name>_traffic.json profiles/<name>_counters.md"
+              % (run_dir.rstrip("/"), copy_mib), "```"]
     lines += ["", "Copy calibration: FETCH_SIZE %.4g KiB and WRITE_SIZE %.4g KiB for %d MiB "
               "read + %d MiB written: scales %.3f (fetch) and %.3f (write)."
               % (cf, cw, copy_mib, copy_mib, f_scale, w_scale),
