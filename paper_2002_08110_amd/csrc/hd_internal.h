@@ -102,6 +102,12 @@ inline bool k3m_used(const hd_solver *s) {
   return s->quad == 0 && s->mapped() && s->plan.kernel == 1 && k3_eligible(s);
 }
 
+// Gauss-Legendre quadrature on mapped cells likewise (kernel 0: the sweep
+// kernel).
+inline bool k3mg_used(const hd_solver *s) {
+  return s->quad == 1 && s->mapped() && s->plan.kernel == 1 && k3_eligible(s);
+}
+
 // Grid, workgroup size and dynamic LDS of one stage launch under the
 // solver's plan.
 hd::LaunchShape shape_of(const hd_solver *s);

@@ -18,6 +18,7 @@
 #include "stage_gauss.h"
 #include "stage_k3_gauss.h"
 #include "stage_k3_mapped.h"
+#include "stage_k3_mgauss.h"
 #include "stage_dispatch.h"
 #include "stage_k3.h"
 
@@ -203,6 +204,12 @@ hd::LaunchShape hd::rt::shape_of(const hd_solver *s) {
     ls.shmem = s->prec == HD_FP32 ? hd::k3m_lds_bytes<float>() : hd::k3m_lds_bytes<double>();
     return ls;
   }
+  if (hd::rt::k3mg_used(s)) {
+    ls.grid = (unsigned)s->ncells;
+    ls.block = 256;
+    ls.shmem = s->prec == HD_FP32 ? hd::k3mg_lds_bytes<float>() : hd::k3mg_lds_bytes<double>();
+    return ls;
+  }
   if (s->quad == 1 || s->mapped()) {
     ls.grid = (unsigned)s->ncells;
     ls.block = (unsigned)hd::gauss_threads((int)s->nd);
@@ -241,6 +248,7 @@ const void *stage_entry(const hd_solver *s, int k3_role) {
   const bool f32 = s->prec == HD_FP32;
   if (k3g_used(s)) return hd::stage_k3g_entry(f32);
   if (k3m_used(s)) return hd::stage_k3m_entry(f32);
+  if (k3mg_used(s)) return hd::stage_k3mg_entry(f32);
   if (s->quad == 1 || s->mapped()) return hd::stage_gauss_entry(s->d, s->n, f32, s->mapped());
   if (s->plan.kernel == 1) return f32 ? hd::stage_k3_f32(s->plan.options, k3_role)
                                       : hd::stage_k3_f64(s->plan.options, k3_role);
@@ -317,14 +325,38 @@ void k3g_tables(const hd::GaussTables1D &g, hd::K3GaussTables<P> *kt) {
   for (int q = 0; q < 4; ++q) kt->g[q] = (P)g.g[q];
 }
 
+// Tables of the mapped Gauss-Legendre kernel in the 6D degree-3 layout: the
+// nodal-form matrices of the Cartesian one, and the Gauss-point weak
+// derivative, traces and lifts.
+template <typename P>
+void k3mg_tables(const hd::GaussTables1D &g, hd::K3MGaussTables<P> *mt) {
+  hd::K3GaussTables<P> kt;
+  k3g_tables(g, &kt);
+  for (int q = 0; q < 16; ++q) {
+    mt->B[q] = kt.B[q];
+    mt->Binv[q] = kt.Binv[q];
+    mt->Dt[q] = kt.Dt[q];
+    mt->G[q] = kt.G[q];
+  }
+  for (int q = 0; q < 4; ++q)
+    for (int m = 0; m < 4; ++m) mt->Dw[q * 4 + m] = (P)(g.Dg[m * 4 + q] * g.om[m] / g.om[q]);
+  for (int sd = 0; sd < 2; ++sd)
+    for (int i = 0; i < 4; ++i) {
+      mt->Blift[sd][i] = kt.Blift[sd][i];
+      mt->ext[sd][i] = (P)g.ext[sd][i];
+      mt->lift[sd][i] = (P)g.lift[sd][i];
+    }
+  for (int q = 0; q < 4; ++q) mt->g[q] = kt.g[q];
+}
+
 template <typename P>
 hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, int mode,
                     int stage, double dt, hipStream_t st) {
   hd::StageParams<P> prm;
   // The sweep kernel (Gauss-Legendre quadrature or mapped cells) reads the
   // fields in their own form, not the specialised kernel's.
-  const bool k3g = hd::rt::k3g_used(s), k3m = hd::rt::k3m_used(s);
-  const bool sweep = (s->quad == 1 || s->mapped()) && !k3g && !k3m;
+  const bool k3g = hd::rt::k3g_used(s), k3m = hd::rt::k3m_used(s), k3mg = hd::rt::k3mg_used(s);
+  const bool sweep = (s->quad == 1 || s->mapped()) && !k3g && !k3m && !k3mg;
   fill_params<P>(s, &prm, sweep ? 0 : s->plan.kernel);
   const hd::LaunchShape ls = hd::rt::shape_of(s);
   prm.nblocks = ls.grid;
@@ -355,7 +387,7 @@ hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, in
   // and late-increment variants measured faster with one slab per XCD at 8^6
   // on data of full entropy (5.86 against 6.00 ms and 5.50 against 5.55 ms),
   // where the general variant is 3% faster with the window order.
-  if (!k3g && !k3m && !sweep && s->plan.kernel == 1 && !f32 && k3_role != 0) prm.xcd_remap = 1;
+  if (!k3g && !k3m && !k3mg && !sweep && s->plan.kernel == 1 && !f32 && k3_role != 0) prm.xcd_remap = 1;
   const void *fn = hd::rt::stage_entry(s, k3_role);
   if (!fn) return fail(HD_ERR_HIP, "no compiled stage kernel for this plan");
   if (s->field_kind == 2) {
@@ -377,8 +409,13 @@ hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, in
   hd::GaussTables<P> gt;
   hd::K3GaussTables<P> kt;
   hd::K3MappedTables<P> km;
-  void *args[] = {&prm, k3g ? (void *)&kt : (k3m ? (void *)&km : (void *)&gt)};
+  hd::K3MGaussTables<P> kmg;
+  void *args[] = {&prm, k3g ? (void *)&kt : (k3m ? (void *)&km : (k3mg ? (void *)&kmg : (void *)&gt))};
   if (k3g) k3g_tables(s->gtab, &kt);
+  if (k3mg) {
+    k3mg_tables(s->gtab, &kmg);
+    prm.xmetric = s->xmetric();
+  }
   if (k3m) {
     // Dw = W^-1 D^T W of the Gauss-Lobatto collocation
     for (int q = 0; q < 4; ++q)

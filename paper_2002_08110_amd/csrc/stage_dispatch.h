@@ -144,6 +144,10 @@ const void *stage_k3g_entry(bool f32);
 // 3, in the same layout (stage_k3_mapped.hip); streaming stores.
 const void *stage_k3m_entry(bool f32);
 
+// Gauss-Legendre quadrature on mapped cells for d = 6 (3 x + 3 v), degree 3,
+// in the same layout (stage_k3_mgauss.hip); streaming stores.
+const void *stage_k3mg_entry(bool f32);
+
 // Sweep kernel (stage_gauss.hip): Gauss-Legendre quadrature on Cartesian
 // cells, or either quadrature on mapped cells; one cell per workgroup;
 // nullptr where the cell's LDS does not fit.

@@ -214,3 +214,46 @@ def test_6d_k3_collocation_rk_steps_on_mapped_cells(precision):
     S.rk_step(dt, case.steps)
     assert rel_l2(S.get_state(), ref) <= (TOL_FP64 if precision == "fp64" else 1e-5)
     S.close()
+
+
+@pytest.mark.parametrize("field", ["constant", "sine", "table"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_6d_k3_gauss_legendre_layout_and_sweep_kernels_match_the_oracle(field, precision):
+    # Mapped 6D degree 3 with Gauss-Legendre quadrature: the kernel in the
+    # collocation kernel's thread layout (plan kernel 1, the default) and the
+    # sweep kernel (kernel 0), both against the oracle's mapped Gauss mode.
+    # One velocity cell spans [-6, 6] in v1 and v2, so x-faces carry inflow
+    # and outflow points side by side.
+    case = case_of(6, 3, field)
+    case.cells = [2, 1, 2, 1, 1, 2]
+    E = W.random_field_table(x_table_size(case), seed=17) if field == "table" else None
+    P = oracle_of(case, E)
+    u = W.random_state(P.ndofs, seed=47)
+    ref = P.apply(u, mode=2)
+    outs = []
+    for kernel in (1, 0):
+        S = solver_of(case, precision, "gauss_legendre", E)
+        S.set_plan(kernel=kernel)
+        out = S.apply(torch.from_numpy(u).cuda()).double().cpu().numpy()
+        tol = TOL_FP64 if precision == "fp64" else 5e-6
+        assert rel_l2(out, ref) <= tol, kernel
+        if precision == "fp64":
+            assert rel_max(out, ref) <= TOL_FP64, kernel
+        outs.append(out)
+        S.close()
+    assert rel_l2(outs[0], outs[1]) <= (1e-13 if precision == "fp64" else 5e-6)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_6d_k3_gauss_legendre_rk_steps_on_mapped_cells(precision):
+    case = W.phase_space_case("p", 3, 3, [2, 1, 1, 2, 1, 1], 3, 2)
+    P = oracle_of(case)
+    S = solver_of(case, precision, "gauss_legendre")
+    assert S.get_plan()["kernel"] == 1
+    u0 = W.random_state(P.ndofs, seed=53)
+    dt = P.stable_dt(case.cfl)
+    ref = P.rk_steps(u0, dt, case.steps, mode=2)
+    S.set_state(u0)
+    S.rk_step(dt, case.steps)
+    assert rel_l2(S.get_state(), ref) <= (TOL_FP64 if precision == "fp64" else 1e-5)
+    S.close()
