@@ -437,7 +437,7 @@ def run_mapped(case, steps, warmup, precisions, eps):
     out["value"] = head["dof_updates_per_s"]
     out["vs_paper_node"] = head["dof_updates_per_s"] / (PAPER_GDOFS_PER_NODE * 1e9)
     gb = head["stage_kernel_GBps"]
-    out["roofline"] = {"bound": "lds", "kernel": "stage_gauss_kernel<6,4,3,double,mapped>",
+    out["roofline"] = {"bound": "alu", "kernel": "stage_k3mg_kernel<double>",
                        "achieved_hbm": gb, "peak_hbm": HBM_PEAK_GBPS, "unit": "GB/s",
                        "frac_hbm": gb / HBM_PEAK_GBPS, "algorithmic_bytes_per_dof": 28.8}
     print(json.dumps(out), flush=True)

@@ -201,7 +201,9 @@ hd_status hd_set_quadrature(hd_solver *s, int quadrature);
  * matrix with |J|; the metric is stored at the x-quadrature points only
  * (per x-cell) and combined with the v-metric on the fly (Sec. 3.3).
  * Diagnostics weight with |J|. Works with either quadrature (one cell per
- * workgroup, as quadrature 1). eps = 0 restores Cartesian cells;
+ * workgroup, as quadrature 1; for d = 6 (3 x + 3 v) at degree 3, plan
+ * kernel 1, the default, runs either quadrature in the specialised
+ * kernel's thread layout and kernel 0 the general one). eps = 0 restores Cartesian cells;
  * |eps| <= 0.05 (HD_ERR_INVALID otherwise, or if |J| <= 0 somewhere).
  * HD_ERR_UNSUPPORTED with the Vlasov-Poisson field, where the kernel's LDS
  * would exceed 160 KiB, and for 5D degree 5 (not compiled). The CFL estimate of hd_stable_dt ignores the

@@ -25,7 +25,9 @@
 //  - at an x-face with inflow points, the jump of the neighbour's trace
 //    against the own one is carried to the face's Gauss points in all five
 //    tangential dimensions, weighted with min(ahat.n, 0) point by point and
-//    returned to nodal form along v.
+//    returned to nodal form along v. (Applying ahat.n in nodal form where a
+//    whole face has inflow, like the volume term, measured slower: 31.2
+//    against 28.2 ms per FP64 stage at 8^6.)
 // The division by |J| acts on the x-terms only (the v-terms are scaled by
 // |J| before they enter Z). Exact up to rounding: the same operator as the
 // sweep kernel's mapped Gauss-Legendre mode and the oracle's mapped
@@ -97,15 +99,9 @@ __device__ __forceinline__ P k3mg_line_sum(P x) {
   return x;
 }
 
-// The value of the lane whose digit LD is E, on every lane of its line.
-template <int LD, int E, typename P>
-__device__ __forceinline__ P k3mg_line_bcast(P x, int l) {
-  if constexpr (LD == 1) return dpp_move<quad_bcast(E)>(x);
-  else if constexpr (LD == 2) return __shfl(x, (l & ~12) | (E << 2), 64);
-  else return __shfl(x, (l & 15) | (E << 4), 64);
-}
-
-// FP64: 2 workgroups per CU (LDS); FP32: 3.
+// FP64: 2 workgroups per CU (LDS), FP32: 3, both with some values spilled
+// (measured faster than one and two without spills: 28.0 against 39.3 ms
+// and 16.7 against 18.9 ms per stage at 8^6).
 template <typename P, int OPT>
 __global__ void __launch_bounds__(256)
     __attribute__((amdgpu_waves_per_eu(sizeof(P) == 8 ? 2 : 3, sizeof(P) == 8 ? 2 : 3)))
@@ -179,10 +175,10 @@ __global__ void __launch_bounds__(256)
   // E at this lane's x-Gauss point (the nodal interpolant)
   k3g_x3<3>(tB, eg, l);
 
-  // Inflow sides. v-faces: from the sign of E at the x-Gauss points. x-face
-  // (j, side): the least of ahat.n = n_s f . v over the velocity Gauss grid,
-  // which separates over the components (linear in each v_c); f is the
-  // adjugate row at this lane's tangential x-point.
+  // Inflow sides (bit 2 j + side). v-faces: from the sign of E at the
+  // x-Gauss points. x-face (j, side): the least of ahat.n = n_s f . v over
+  // the velocity Gauss grid, which separates over the components (linear in
+  // each v_c); f is the adjugate row at this lane's tangential x-point.
   {
     int mine = 0;
 #pragma unroll
@@ -220,24 +216,35 @@ __global__ void __launch_bounds__(256)
   __syncthreads();  // cell, Ux, mask
   const int active = fmask;
 
-  // ---- volume, v-dimensions (strong form), scaled by |J| ----
-  P z[16];
+  // ---- volume, v-dimensions (strong form), scaled by |J|; from the same
+  // values along i4, V1 = (alpha_1 I + vh_1 G) Ux along i4 ----
+  P z[16], V1[16];
   {
     const P c4 = det * prm.inv_h[3] * eg[0], c5 = det * prm.inv_h[4] * eg[1],
             c6 = det * prm.inv_h[5] * eg[2];
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       const int i5 = s & 3, i6 = s >> 2;
-      P d4 = P(0), d5 = P(0), d6 = P(0);
+      P d4 = P(0), d5 = P(0), d6 = P(0), g1 = P(0);
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        d4 += tDt[w * 4 + m] * uxb[l + 64 * m + 256 * s];
+        const P x = uxb[l + 64 * m + 256 * s];
+        d4 += tDt[w * 4 + m] * x;
+        g1 += tG[w * 4 + m] * x;
         d5 += mt.Dt[i5 * 4 + m] * ux[4 * i6 + m];
         d6 += mt.Dt[i6 * 4 + m] * ux[i5 + 4 * m];
       }
       z[s] = -(c4 * d4 + c5 * d5 + c6 * d6);
+      V1[s] = alpha[0] * ux[s] + vhh[0] * g1;
     }
   }
+
+  // V1 to LDS in place of Ux (every wave has read Ux along i4): the
+  // registers stay free for the x-passes, which read back their own values.
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < 16; ++s) uxb[t + 256 * s] = V1[s];
+  asm volatile("" ::: "memory");
 
   // ---- x-dimensions: weak volume term and the own traces of both faces ----
 #pragma unroll
@@ -255,19 +262,18 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       const int i5 = s & 3, i6 = s >> 2;
-      P g1 = P(0), g2 = P(0), g3 = P(0);
+      P g2 = P(0), g3 = P(0);
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        g1 += tG[w * 4 + m] * uxb[l + 64 * m + 256 * s];
         g2 += mt.G[i5 * 4 + m] * ux[4 * i6 + m];
         g3 += mt.G[i6 * 4 + m] * ux[i5 + 4 * m];
       }
-      const P V1 = alpha[0] * ux[s] + vhh[0] * g1;
+      const P V1s = uxb[t + 256 * s];
       const P V2 = alpha[1] * ux[s] + vhh[1] * g2;
       const P V3 = alpha[2] * ux[s] + vhh[2] * g3;
-      p[s] = a0 * V1 + a1 * V2 + a2 * V3;
-      P w0 = e0 * (f00 * V1 + f01 * V2 + f02 * V3);
-      P w1 = e1 * (f10 * V1 + f11 * V2 + f12 * V3);
+      p[s] = a0 * V1s + a1 * V2 + a2 * V3;
+      P w0 = e0 * (f00 * V1s + f01 * V2 + f02 * V3);
+      P w1 = e1 * (f10 * V1s + f11 * V2 + f12 * V3);
       if (j == 0) {
         w0 = k3mg_line_sum<1>(w0);
         w1 = k3mg_line_sum<1>(w1);
@@ -291,7 +297,7 @@ __global__ void __launch_bounds__(256)
   // ---- faces of the v-dimensions: upwind jumps (Cartesian form), scaled by |J| ----
 #pragma unroll
   for (int j = 3; j < 6; ++j) {
-#pragma unroll
+#pragma unroll 1
     for (int sd = 0; sd < 2; ++sd) {
       if (!((active >> (2 * j + sd)) & 1)) continue;
       // face node p = t + 256 q: the own-minus-neighbour nodal jump
@@ -333,81 +339,81 @@ __global__ void __launch_bounds__(256)
   }
 
   // ---- x-faces with inflow points: min(ahat.n, 0) (u_nbr - u_own) ----
+  // One copy of the code for the six sides (dimension and side at run time,
+  // uniform over the workgroup): the kernel's code stays small enough for
+  // the instruction cache.
+#pragma unroll 1
+  for (int f = 0; f < 6; ++f) {
+    const int j = f >> 1, sd = f & 1;
+    if (!((active >> f) & 1)) continue;
+    const int sj = 1 << (2 * j);
+    const int ij = (l >> (2 * j)) & 3;
+    const int tl = l % sj + (l / (sj * 4)) * sj;  // the face's tangential x-point
+    const bool fl = ij == (sd ? 3 : 0);            // this lane holds face nodes
+    const unsigned cj = (cell / prm.cstride[j]) % prm.cells[j], nj = prm.cells[j], stj = prm.cstride[j];
+    const unsigned nbr = sd ? (cj == nj - 1 ? cell - (nj - 1) * stj : cell + stj)
+                            : (cj == 0 ? cell + (nj - 1) * stj : cell - stj);
+    P jv[16];
+    if (fl) {
+      const double *un = prm.u_in + (uint64_t)nbr * ND;
+      const int nl = sd ? l - 3 * sj : l + 3 * sj;  // the neighbour's node across
 #pragma unroll
-  for (int j = 0; j < 3; ++j) {
+      for (int s = 0; s < 16; ++s) jv[s] = to_p<P>(un[nl + 64 * w + 256 * s]) - cellb[t + 256 * s];
+    } else {
 #pragma unroll
-    for (int sd = 0; sd < 2; ++sd) {
-      if (!((active >> (2 * j + sd)) & 1)) continue;
-      const int sj = 1 << (2 * j);
-      const int ij = j == 0 ? i1 : (j == 1 ? i2 : i3);
-      const int tl = l % sj + (l / (sj * 4)) * sj;  // the face's tangential x-point
-      const bool fl = ij == (sd ? 3 : 0);            // this lane holds face nodes
-      P jv[16];
-      if (fl) {
-        const double *un = prm.u_in + (uint64_t)(sd ? right[j] : left[j]) * ND;
-        const int nl = sd ? l - 3 * sj : l + 3 * sj;  // the neighbour's node across
+      for (int s = 0; s < 16; ++s) jv[s] = P(0);
+    }
+    // to the x-Gauss points along the two tangential lane dimensions
+    if (j != 0) k3g_lane<1, 16>(tB, jv, l);
+    if (j != 1) k3g_lane<2, 16>(tB, jv, l);
+    if (j != 2) k3g_lane<3, 16>(tB, jv, l);
+    const double *mf = mg + 64 * MXE + (f * NFX + tl) * 3;
+    const P fa = sd ? (P)mf[0] : -(P)mf[0], fb = sd ? (P)mf[1] : -(P)mf[1],
+            fc = sd ? (P)mf[2] : -(P)mf[2];
+    // the jump at the face's velocity Gauss points, weighted point by point
+    // with min(ahat.n, 0), and back to nodal form along v
+    k3mg_reg5(mt.B, jv);
+    k3mg_reg6(mt.B, jv);
+    __syncthreads();  // earlier readers of the face buffer are done
+    if (fl) {
 #pragma unroll
-        for (int s = 0; s < 16; ++s) jv[s] = to_p<P>(un[nl + 64 * w + 256 * s]) - cellb[t + 256 * s];
-      } else {
-#pragma unroll
-        for (int s = 0; s < 16; ++s) jv[s] = P(0);
-      }
-      // to the Gauss points: the two tangential lane dimensions, i5, i6, i4
-      if (j != 0) k3g_lane<1, 16>(tB, jv, l);
-      if (j != 1) k3g_lane<2, 16>(tB, jv, l);
-      if (j != 2) k3g_lane<3, 16>(tB, jv, l);
-      k3mg_reg5(mt.B, jv);
-      k3mg_reg6(mt.B, jv);
-      __syncthreads();  // earlier readers of the face buffer are done
-      if (fl) {
-#pragma unroll
-        for (int s = 0; s < 16; ++s) faceb[tl + 16 * w + 64 * s] = jv[s];
-      }
-      __syncthreads();
-      if (fl) {
-        const double *mf = mg + 64 * MXE + ((j * 2 + sd) * NFX + tl) * 3;
-        const P fa = sd ? (P)mf[0] : -(P)mf[0], fb = sd ? (P)mf[1] : -(P)mf[1],
-                fc = sd ? (P)mf[2] : -(P)mf[2];
-        const P v1 = alpha[0] + vhh[0] * tg[w];
-#pragma unroll
-        for (int s = 0; s < 16; ++s) {
-          const int i5 = s & 3, i6 = s >> 2;
-          P x = P(0);
-#pragma unroll
-          for (int m = 0; m < 4; ++m) x += tB[w * 4 + m] * faceb[tl + 16 * m + 64 * s];
-          const P an = fa * v1 + fb * (alpha[1] + vhh[1] * mt.g[i5]) + fc * (alpha[2] + vhh[2] * mt.g[i6]);
-          jv[s] = (an < P(0) ? an : P(0)) * x;
-        }
-      }
-      // back to nodal form along v: i5, i6 in registers, i4 via LDS
-      k3mg_reg5(mt.Binv, jv);
-      k3mg_reg6(mt.Binv, jv);
-      __syncthreads();  // the forward values are read
-      if (fl) {
-#pragma unroll
-        for (int s = 0; s < 16; ++s) faceb[tl + 16 * w + 64 * s] = jv[s];
-      }
-      __syncthreads();
-      if (fl) {
-#pragma unroll
-        for (int s = 0; s < 16; ++s) {
-          P x = P(0);
-#pragma unroll
-          for (int m = 0; m < 4; ++m) x += tBinv[w * 4 + m] * faceb[tl + 16 * m + 64 * s];
-          jv[s] = x;
-        }
-      }
-      // lift along x_j from the face lane to its line: - lift_s[q_j] F
-      const P lq = tLift[4 * sd + ij];
+      for (int s = 0; s < 16; ++s) faceb[tl + 16 * w + 64 * s] = jv[s];
+    }
+    __syncthreads();
+    if (fl) {
+      const P v1 = alpha[0] + vhh[0] * tg[w];
 #pragma unroll
       for (int s = 0; s < 16; ++s) {
-        P fv;
-        if (j == 0) fv = sd ? k3mg_line_bcast<1, 3>(jv[s], l) : k3mg_line_bcast<1, 0>(jv[s], l);
-        else if (j == 1) fv = sd ? k3mg_line_bcast<2, 3>(jv[s], l) : k3mg_line_bcast<2, 0>(jv[s], l);
-        else fv = sd ? k3mg_line_bcast<3, 3>(jv[s], l) : k3mg_line_bcast<3, 0>(jv[s], l);
-        z[s] -= lq * fv;
+        const int i5 = s & 3, i6 = s >> 2;
+        P x = P(0);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) x += tB[w * 4 + m] * faceb[tl + 16 * m + 64 * s];
+        const P an = fa * v1 + fb * (alpha[1] + vhh[1] * mt.g[i5]) + fc * (alpha[2] + vhh[2] * mt.g[i6]);
+        jv[s] = (an < P(0) ? an : P(0)) * x;
       }
     }
+    k3mg_reg5(mt.Binv, jv);
+    k3mg_reg6(mt.Binv, jv);
+    __syncthreads();  // the forward values are read
+    if (fl) {
+#pragma unroll
+      for (int s = 0; s < 16; ++s) faceb[tl + 16 * w + 64 * s] = jv[s];
+    }
+    __syncthreads();
+    if (fl) {
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        P x = P(0);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) x += tBinv[w * 4 + m] * faceb[tl + 16 * m + 64 * s];
+        jv[s] = x;
+      }
+    }
+    // lift along x_j from the face lane to its line: - lift_s[q_j] F
+    const P lq = tLift[4 * sd + ij];
+    const int src = (l & ~(3 << (2 * j))) | ((3 * sd) << (2 * j));
+#pragma unroll
+    for (int s = 0; s < 16; ++s) z[s] -= lq * __shfl(jv[s], src, 64);
   }
 
   // ---- division by |J|, back to the x-nodes ----
