@@ -294,6 +294,26 @@ __global__ void __launch_bounds__(256)
     for (int s = 0; s < 16; ++s) z[s] += p[s];
   }
 
+  // Neighbour layer of an x-face (face lanes only, raw FP64): the first
+  // active face's is loaded before the x-face loop, each next one at the
+  // start of the previous face's work, so that their latency overlaps work.
+  // (Loaded before the v-faces instead, the buffer live across them sent
+  // the register allocation to scratch.)
+  double nx[16];
+  int fnext = active & 63 ? __builtin_ctz(active & 63) : 6;
+#define K3MG_LOAD_FACE(F)                                                                          \
+  {                                                                                                \
+    const int j_ = (F) >> 1, sd_ = (F) & 1, sj_ = 1 << (2 * j_);                                   \
+    if (((l >> (2 * j_)) & 3) == (sd_ ? 3 : 0)) {                                                  \
+      const unsigned cj_ = (cell / prm.cstride[j_]) % prm.cells[j_], nj_ = prm.cells[j_],         \
+                     st_ = prm.cstride[j_];                                                        \
+      const unsigned nb_ = sd_ ? (cj_ == nj_ - 1 ? cell - (nj_ - 1) * st_ : cell + st_)            \
+                               : (cj_ == 0 ? cell + (nj_ - 1) * st_ : cell - st_);                 \
+      const double *un_ = prm.u_in + (uint64_t)nb_ * ND + (sd_ ? l - 3 * sj_ : l + 3 * sj_) + 64 * w; \
+      _Pragma("unroll") for (int s = 0; s < 16; ++s) nx[s] = un_[256 * s];                         \
+    }                                                                                              \
+  }
+
   // ---- faces of the v-dimensions: upwind jumps (Cartesian form), scaled by |J| ----
 #pragma unroll
   for (int j = 3; j < 6; ++j) {
@@ -342,27 +362,27 @@ __global__ void __launch_bounds__(256)
   // One copy of the code for the six sides (dimension and side at run time,
   // uniform over the workgroup): the kernel's code stays small enough for
   // the instruction cache.
+  if (fnext < 6) K3MG_LOAD_FACE(fnext)
 #pragma unroll 1
-  for (int f = 0; f < 6; ++f) {
+  for (int f = fnext; f < 6; f = fnext) {
     const int j = f >> 1, sd = f & 1;
-    if (!((active >> f) & 1)) continue;
     const int sj = 1 << (2 * j);
     const int ij = (l >> (2 * j)) & 3;
     const int tl = l % sj + (l / (sj * 4)) * sj;  // the face's tangential x-point
     const bool fl = ij == (sd ? 3 : 0);            // this lane holds face nodes
-    const unsigned cj = (cell / prm.cstride[j]) % prm.cells[j], nj = prm.cells[j], stj = prm.cstride[j];
-    const unsigned nbr = sd ? (cj == nj - 1 ? cell - (nj - 1) * stj : cell + stj)
-                            : (cj == 0 ? cell + (nj - 1) * stj : cell - stj);
     P jv[16];
     if (fl) {
-      const double *un = prm.u_in + (uint64_t)nbr * ND;
-      const int nl = sd ? l - 3 * sj : l + 3 * sj;  // the neighbour's node across
 #pragma unroll
-      for (int s = 0; s < 16; ++s) jv[s] = to_p<P>(un[nl + 64 * w + 256 * s]) - cellb[t + 256 * s];
+      for (int s = 0; s < 16; ++s) jv[s] = to_p<P>(nx[s]) - cellb[t + 256 * s];
     } else {
 #pragma unroll
       for (int s = 0; s < 16; ++s) jv[s] = P(0);
     }
+    {
+      const int rest = active & 63 & ~((2 << f) - 1);
+      fnext = rest ? __builtin_ctz(rest) : 6;
+    }
+    if (fnext < 6) K3MG_LOAD_FACE(fnext)
     // to the x-Gauss points along the two tangential lane dimensions
     if (j != 0) k3g_lane<1, 16>(tB, jv, l);
     if (j != 1) k3g_lane<2, 16>(tB, jv, l);
@@ -415,6 +435,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int s = 0; s < 16; ++s) z[s] -= lq * __shfl(jv[s], src, 64);
   }
+#undef K3MG_LOAD_FACE
 
   // ---- division by |J|, back to the x-nodes ----
   const P rdet = P(1) / det;
