@@ -289,3 +289,17 @@ def test_tune_plan_keeps_the_state_and_steps_as_the_fixed_plan(d, k, precision):
     assert np.array_equal(S.get_state(), T.get_state())
     S.close()
     T.close()
+
+
+def test_tune_plan_keeps_the_plan_it_had_within_the_margin():
+    # A candidate replaces the plan the solver had only when it is faster by
+    # more than the margin; with a margin of 1 none can be.
+    case = small_case(6, 3, "sine")
+    S = gpu_solver(case, "fp64")
+    start = S.get_plan()
+    u0 = W.random_state(S.ndofs, seed=37)
+    S.set_state(u0)
+    assert S.tune_plan(S.stable_dt(0.2), margin=1.0) == start
+    assert S.get_plan() == start
+    assert np.array_equal(S.get_state(), u0)
+    S.close()
