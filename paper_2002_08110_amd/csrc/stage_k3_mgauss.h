@@ -25,9 +25,9 @@
 //  - at an x-face with inflow points, the jump of the neighbour's trace
 //    against the own one is carried to the face's Gauss points in all five
 //    tangential dimensions, weighted with min(ahat.n, 0) point by point and
-//    returned to nodal form along v. (Applying ahat.n in nodal form where a
-//    whole face has inflow, like the volume term, measured slower: 31.2
-//    against 28.2 ms per FP64 stage at 8^6.)
+//    returned to nodal form along v; each wave takes one face's layer whole.
+//    (Applying ahat.n in nodal form where a whole face has inflow, like the
+//    volume term, measured slower.)
 // The division by |J| acts on the x-terms only (the v-terms are scaled by
 // |J| before they enter Z). Exact up to rounding: the same operator as the
 // sweep kernel's mapped Gauss-Legendre mode and the oracle's mapped
@@ -294,26 +294,6 @@ __global__ void __launch_bounds__(256)
     for (int s = 0; s < 16; ++s) z[s] += p[s];
   }
 
-  // Neighbour layer of an x-face (face lanes only, raw FP64): the first
-  // active face's is loaded before the x-face loop, each next one at the
-  // start of the previous face's work, so that their latency overlaps work.
-  // (Loaded before the v-faces instead, the buffer live across them sent
-  // the register allocation to scratch.)
-  double nx[16];
-  int fnext = active & 63 ? __builtin_ctz(active & 63) : 6;
-#define K3MG_LOAD_FACE(F)                                                                          \
-  {                                                                                                \
-    const int j_ = (F) >> 1, sd_ = (F) & 1, sj_ = 1 << (2 * j_);                                   \
-    if (((l >> (2 * j_)) & 3) == (sd_ ? 3 : 0)) {                                                  \
-      const unsigned cj_ = (cell / prm.cstride[j_]) % prm.cells[j_], nj_ = prm.cells[j_],         \
-                     st_ = prm.cstride[j_];                                                        \
-      const unsigned nb_ = sd_ ? (cj_ == nj_ - 1 ? cell - (nj_ - 1) * st_ : cell + st_)            \
-                               : (cj_ == 0 ? cell + (nj_ - 1) * st_ : cell - st_);                 \
-      const double *un_ = prm.u_in + (uint64_t)nb_ * ND + (sd_ ? l - 3 * sj_ : l + 3 * sj_) + 64 * w; \
-      _Pragma("unroll") for (int s = 0; s < 16; ++s) nx[s] = un_[256 * s];                         \
-    }                                                                                              \
-  }
-
   // ---- faces of the v-dimensions: upwind jumps (Cartesian form), scaled by |J| ----
 #pragma unroll
   for (int j = 3; j < 6; ++j) {
@@ -359,83 +339,104 @@ __global__ void __launch_bounds__(256)
   }
 
   // ---- x-faces with inflow points: min(ahat.n, 0) (u_nbr - u_own) ----
-  // One copy of the code for the six sides (dimension and side at run time,
-  // uniform over the workgroup): the kernel's code stays small enough for
-  // the instruction cache.
-  if (fnext < 6) K3MG_LOAD_FACE(fnext)
+  // Rounds of up to four active faces. Face point p = t + 256 q of x-face j
+  // has the digits (tangential x, i4, i5, i6) = p, so the workgroup writes
+  // the nodal jumps of a face into a 1024-value slot (the buffer of V1,
+  // free now); wave k then holds slot k whole, 64 lanes (tangential x, i4)
+  // by 16 registers (i5, i6), carries it to the Gauss points in all five
+  // dimensions with lane and register transforms, weights it with
+  // min(ahat.n, 0) and returns it to nodal form along v; every thread then
+  // lifts its line's values along x_j.
+  int pending = active & 63;
 #pragma unroll 1
-  for (int f = fnext; f < 6; f = fnext) {
-    const int j = f >> 1, sd = f & 1;
-    const int sj = 1 << (2 * j);
-    const int ij = (l >> (2 * j)) & 3;
-    const int tl = l % sj + (l / (sj * 4)) * sj;  // the face's tangential x-point
-    const bool fl = ij == (sd ? 3 : 0);            // this lane holds face nodes
-    P jv[16];
-    if (fl) {
-#pragma unroll
-      for (int s = 0; s < 16; ++s) jv[s] = to_p<P>(nx[s]) - cellb[t + 256 * s];
-    } else {
-#pragma unroll
-      for (int s = 0; s < 16; ++s) jv[s] = P(0);
-    }
+  while (pending) {
+    int round = 0, cnt = 0;
     {
-      const int rest = active & 63 & ~((2 << f) - 1);
-      fnext = rest ? __builtin_ctz(rest) : 6;
+      int r = pending;
+      while (r && cnt < 4) {
+        round |= r & -r;
+        r &= r - 1;
+        ++cnt;
+      }
     }
-    if (fnext < 6) K3MG_LOAD_FACE(fnext)
-    // to the x-Gauss points along the two tangential lane dimensions
-    if (j != 0) k3g_lane<1, 16>(tB, jv, l);
-    if (j != 1) k3g_lane<2, 16>(tB, jv, l);
-    if (j != 2) k3g_lane<3, 16>(tB, jv, l);
-    const double *mf = mg + 64 * MXE + (f * NFX + tl) * 3;
-    const P fa = sd ? (P)mf[0] : -(P)mf[0], fb = sd ? (P)mf[1] : -(P)mf[1],
-            fc = sd ? (P)mf[2] : -(P)mf[2];
-    // the jump at the face's velocity Gauss points, weighted point by point
-    // with min(ahat.n, 0), and back to nodal form along v
-    k3mg_reg5(mt.B, jv);
-    k3mg_reg6(mt.B, jv);
-    __syncthreads();  // earlier readers of the face buffer are done
-    if (fl) {
+    pending &= ~round;
+    // the neighbour layers of the round's faces, all loads in flight at once
+    double nb[6][4];
 #pragma unroll
-      for (int s = 0; s < 16; ++s) faceb[tl + 16 * w + 64 * s] = jv[s];
+    for (int f = 0; f < 6; ++f) {
+      if (!((round >> f) & 1)) continue;
+      const int j = f >> 1, sd = f & 1;
+      const unsigned nbr = sd ? right[j] : left[j];
+      const double *un = prm.u_in + (uint64_t)nbr * ND;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int node0 = k3_face_node0(t + 256 * q, j);
+        nb[f][q] = un[sd ? node0 : node0 + 3 * (1 << (2 * j))];
+      }
+    }
+    __syncthreads();  // earlier readers of the slots are done
+    {
+      P *slot = uxb;
+#pragma unroll
+      for (int f = 0; f < 6; ++f) {
+        if (!((round >> f) & 1)) continue;
+        const int j = f >> 1, sd = f & 1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int node0 = k3_face_node0(t + 256 * q, j);
+          slot[t + 256 * q] = to_p<P>(nb[f][q]) - cellb[sd ? node0 + 3 * (1 << (2 * j)) : node0];
+        }
+        slot += kK3Face;
+      }
     }
     __syncthreads();
-    if (fl) {
-      const P v1 = alpha[0] + vhh[0] * tg[w];
+    if (w < cnt) {
+      // this wave's face: the w-th of the round
+      int r = round;
+      for (int i = 0; i < w; ++i) r &= r - 1;
+      const int f = __builtin_ctz(r), sd = f & 1;
+      P *slot = uxb + kK3Face * w;
+      P jv[16];
+#pragma unroll
+      for (int s = 0; s < 16; ++s) jv[s] = slot[l + 64 * s];
+      k3g_lane<1, 16>(tB, jv, l);  // tangential x (lower dimension)
+      k3g_lane<2, 16>(tB, jv, l);  // tangential x (upper dimension)
+      k3g_lane<3, 16>(tB, jv, l);  // i4
+      k3mg_reg5(mt.B, jv);
+      k3mg_reg6(mt.B, jv);
+      const double *mf = mg + 64 * MXE + (f * NFX + (l & 15)) * 3;
+      const P fa = sd ? (P)mf[0] : -(P)mf[0], fb = sd ? (P)mf[1] : -(P)mf[1],
+              fc = sd ? (P)mf[2] : -(P)mf[2];
+      const P v1 = alpha[0] + vhh[0] * tg[l >> 4];
 #pragma unroll
       for (int s = 0; s < 16; ++s) {
         const int i5 = s & 3, i6 = s >> 2;
-        P x = P(0);
-#pragma unroll
-        for (int m = 0; m < 4; ++m) x += tB[w * 4 + m] * faceb[tl + 16 * m + 64 * s];
         const P an = fa * v1 + fb * (alpha[1] + vhh[1] * mt.g[i5]) + fc * (alpha[2] + vhh[2] * mt.g[i6]);
-        jv[s] = (an < P(0) ? an : P(0)) * x;
+        jv[s] *= an < P(0) ? an : P(0);
       }
-    }
-    k3mg_reg5(mt.Binv, jv);
-    k3mg_reg6(mt.Binv, jv);
-    __syncthreads();  // the forward values are read
-    if (fl) {
+      k3g_lane<3, 16>(tBinv, jv, l);
+      k3mg_reg5(mt.Binv, jv);
+      k3mg_reg6(mt.Binv, jv);
 #pragma unroll
-      for (int s = 0; s < 16; ++s) faceb[tl + 16 * w + 64 * s] = jv[s];
+      for (int s = 0; s < 16; ++s) slot[l + 64 * s] = jv[s];
     }
     __syncthreads();
-    if (fl) {
+    // lift along x_j: - lift_s[q_j] F at the line's face point
+    {
+      const P *slot = uxb;
 #pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        P x = P(0);
+      for (int f = 0; f < 6; ++f) {
+        if (!((round >> f) & 1)) continue;
+        const int j = f >> 1, sd = f & 1, sj = 1 << (2 * j);
+        const int ij = (l >> (2 * j)) & 3;
+        const int tl = l % sj + (l / (sj * 4)) * sj;
+        const P lq = tLift[4 * sd + ij];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) x += tBinv[w * 4 + m] * faceb[tl + 16 * m + 64 * s];
-        jv[s] = x;
+        for (int s = 0; s < 16; ++s) z[s] -= lq * slot[tl + 16 * w + 64 * s];
+        slot += kK3Face;
       }
     }
-    // lift along x_j from the face lane to its line: - lift_s[q_j] F
-    const P lq = tLift[4 * sd + ij];
-    const int src = (l & ~(3 << (2 * j))) | ((3 * sd) << (2 * j));
-#pragma unroll
-    for (int s = 0; s < 16; ++s) z[s] -= lq * __shfl(jv[s], src, 64);
   }
-#undef K3MG_LOAD_FACE
 
   // ---- division by |J|, back to the x-nodes ----
   const P rdet = P(1) / det;
