@@ -99,12 +99,12 @@ __device__ __forceinline__ P k3mg_line_sum(P x) {
   return x;
 }
 
-// FP64: 2 workgroups per CU (LDS), FP32: 3, both with some values spilled
-// (measured faster than one and two without spills: 28.0 against 39.3 ms
-// and 16.7 against 18.9 ms per stage at 8^6).
+// Two workgroups per CU in both precisions (FP64: the LDS; the FP64 kernel
+// spills some values, still faster than one workgroup without spills; FP32
+// without spills, faster than three with them: 14.6 against 15.9 ms per
+// stage at 8^6).
 template <typename P, int OPT>
-__global__ void __launch_bounds__(256)
-    __attribute__((amdgpu_waves_per_eu(sizeof(P) == 8 ? 2 : 3, sizeof(P) == 8 ? 2 : 3)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
     stage_k3mg_kernel(const StageParams<P> prm, const K3MGaussTables<P> mt) {
   constexpr bool NT = (OPT & kOptStream) != 0;
   constexpr int ND = kK3Nodes;
