@@ -84,8 +84,11 @@ typedef struct hd_batch hd_batch;    /* opaque */
  *              kernel specialised for d = 6 (3 x + 3 v) at degree 3, one cell
  *              per 256-thread workgroup (only xcd_remap and options apply;
  *              its FP64 first- and last-stage variants always take one slab
- *              per XCD). Under quadrature 1 it selects the Gauss-Legendre
- *              kernel of the same layout (see hd_set_quadrature).
+ *              per XCD). Under quadrature 1, or on mapped cells (see
+ *              hd_set_mapping), it selects the kernel of the same layout for
+ *              that discretization (Gauss-Legendre, mapped collocation or
+ *              mapped Gauss-Legendre; xcd_remap and the streaming stores
+ *              apply).
  *  options:    bit 0 (both kernels): non-temporal (streaming) loads and
  *              stores of the stage increment du and stores of the output
  *              solution, so they do not displace cached neighbour data;
