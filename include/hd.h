@@ -88,7 +88,8 @@ typedef struct hd_batch hd_batch;    /* opaque */
  *              hd_set_mapping), it selects the kernel of the same layout for
  *              that discretization (Gauss-Legendre, mapped collocation or
  *              mapped Gauss-Legendre; xcd_remap and the streaming stores
- *              apply).
+ *              apply, except that mapped collocation always takes one slab
+ *              per XCD).
  *  options:    bit 0 (both kernels): non-temporal (streaming) loads and
  *              stores of the stage increment du and stores of the output
  *              solution, so they do not displace cached neighbour data;

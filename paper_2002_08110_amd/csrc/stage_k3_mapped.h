@@ -184,12 +184,17 @@ __global__ void __launch_bounds__(256)
       const P f0 = (P)mf[0], f1 = (P)mf[1], f2 = (P)mf[2];
       const double *un = prm.u_in + (uint64_t)(side ? right[j] : left[j]) * ND;
       const int nl = side ? l - 3 * sj : l + 3 * sj;  // digit j: 3 <-> 0
+      // the neighbour's 16 values in one batch of loads (a load per inflow
+      // node, under its own condition, kept them in flight one at a time:
+      // 10.6 against 7.1 ms per FP32 stage at 8^6)
+      double nbv[16];
+#pragma unroll
+      for (int s = 0; s < 16; ++s) nbv[s] = un[nl + 64 * w + 256 * s];
 #pragma unroll
       for (int s = 0; s < 16; ++s) {
         const P a = f0 * v1 + f1 * v2(s) + f2 * v3(s);
         const P an = side ? a : -a;
-        P us = u[s];
-        if (an < P(0)) us = to_p<P>(un[nl + 64 * w + 256 * s]);
+        const P us = an < P(0) ? to_p<P>(nbv[s]) : u[s];
         y[s] -= winv * an * us;
       }
     }
