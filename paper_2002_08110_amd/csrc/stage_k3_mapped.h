@@ -184,17 +184,26 @@ __global__ void __launch_bounds__(256)
       const P f0 = (P)mf[0], f1 = (P)mf[1], f2 = (P)mf[2];
       const double *un = prm.u_in + (uint64_t)(side ? right[j] : left[j]) * ND;
       const int nl = side ? l - 3 * sj : l + 3 * sj;  // digit j: 3 <-> 0
-      // the neighbour's 16 values in one batch of loads (a load per inflow
-      // node, under its own condition, kept them in flight one at a time:
-      // 10.6 against 7.1 ms per FP32 stage at 8^6)
+      // FP32: whether any of the lane's 16 face nodes has inflow, from the
+      // least of a^ . n over its (v2, v3) nodes, which separates over the
+      // two components and sits at the cell's end nodes (6.8 against 7.1 ms
+      // per stage at 8^6; FP64 measured 8.7 against 8.5 ms and loads always).
+      const P g0 = side ? f0 : -f0, g1 = side ? f1 : -f1, g2 = side ? f2 : -f2;
+      const P m2a = g1 * v2(0), m2b = g1 * v2(3), m3a = g2 * v3(0), m3b = g2 * v3(12);
+      const bool need = sizeof(P) == 8 || g0 * v1 + (m2a < m2b ? m2a : m2b) + (m3a < m3b ? m3a : m3b) < P(0);
+      // then the neighbour's 16 values in one batch of loads (a load per
+      // inflow node, under its own condition, kept them in flight one at a
+      // time: 10.6 against 7.1 ms per FP32 stage at 8^6)
       double nbv[16];
+      if (need) {
 #pragma unroll
-      for (int s = 0; s < 16; ++s) nbv[s] = un[nl + 64 * w + 256 * s];
+        for (int s = 0; s < 16; ++s) nbv[s] = un[nl + 64 * w + 256 * s];
+      }
 #pragma unroll
       for (int s = 0; s < 16; ++s) {
         const P a = f0 * v1 + f1 * v2(s) + f2 * v3(s);
         const P an = side ? a : -a;
-        const P us = an < P(0) ? to_p<P>(nbv[s]) : u[s];
+        const P us = need && an < P(0) ? to_p<P>(nbv[s]) : u[s];
         y[s] -= winv * an * us;
       }
     }
