@@ -397,7 +397,11 @@ typedef struct {
   int *multi;    /* multi-index of every node: multi[q * d + m] (mode 2) */
 } or_scratch;
 
-static void eval_cell(const or_geom *g, const or_field *f, int mode,
+/* Zero-skipping evaluation (mode 1) of the weak form on Cartesian cells: the
+ * same sums as the full evaluation, with the terms whose basis value or
+ * derivative is structurally zero left out (the full sums for every mesh are
+ * in eval_cell_general). */
+static void eval_cell(const or_geom *g, const or_field *f,
                       const double *u, int64_t c, double *out, or_scratch *s) {
   const int d = g->d, k = g->k;
   const int64_t nd = g->nd;
@@ -413,41 +417,22 @@ static void eval_cell(const or_geom *g, const or_field *f, int mode,
   /* Step 2 of Algorithm 2, interpolation: u_h(x_q) = sum_i' u_i' phi_i'(x_q). */
   for (int64_t q = 0; q < nd; ++q) {
     node_multi(g, q, qm);
-    double v = 0.0;
-    if (mode == 0) {
-      for (int64_t ip = 0; ip < nd; ++ip) {
-        node_multi(g, ip, im);
-        v += uc[ip] * phi_at(g, im, qm);
-      }
-    } else {
-      /* Only phi_q is nonzero at x_q (nodal basis, collocated points). */
-      v = uc[q] * phi_at(g, qm, qm);
-    }
-    s->uh[q] = v;
+    /* Only phi_q is nonzero at x_q (nodal basis, collocated points). */
+    s->uh[q] = uc[q] * phi_at(g, qm, qm);
   }
 
   /* Volume term V_i = sum_q W_q grad phi_i(x_q) . a(x_q) u_h(x_q). */
   for (int64_t i = 0; i < nd; ++i) {
     node_multi(g, i, im);
     double v = 0.0;
-    if (mode == 0) {
-      for (int64_t q = 0; q < nd; ++q) {
-        node_multi(g, q, qm);
-        double W = vol_weight(g, qm);
-        for (int j = 0; j < d; ++j)
-          v += W * dphi_at(g, im, qm, j) * s->acell[q * d + j] * s->uh[q];
+    /* d/dx_j phi_i vanishes at x_q unless q agrees with i off dim j. */
+    for (int j = 0; j < d; ++j)
+      for (int r = 0; r <= k; ++r) {
+        for (int m = 0; m < d; ++m) qm[m] = im[m];
+        qm[j] = r;
+        int64_t q = node_linear(g, qm);
+        v += vol_weight(g, qm) * dphi_at(g, im, qm, j) * s->acell[q * d + j] * s->uh[q];
       }
-    } else {
-      /* d/dx_j phi_i vanishes at x_q unless q agrees with i off dim j. */
-      for (int j = 0; j < d; ++j)
-        for (int r = 0; r <= k; ++r) {
-          for (int m = 0; m < d; ++m) qm[m] = im[m];
-          qm[j] = r;
-          int64_t q = node_linear(g, qm);
-          v += vol_weight(g, qm) * dphi_at(g, im, qm, j) * s->acell[q * d + j] *
-               s->uh[q];
-        }
-    }
     s->rhs[i] = v;
   }
 
@@ -463,41 +448,20 @@ static void eval_cell(const or_geom *g, const or_field *f, int mode,
       for (int64_t p = 0; p < nd; ++p) {
         node_multi(g, p, pm);
         if (pm[j] != pj) continue; /* face points: nodes with q_j on the face */
-        double uown, unbr;
-        if (mode == 0) {
-          uown = 0.0;
-          unbr = 0.0;
-          for (int64_t ip = 0; ip < nd; ++ip) {
-            node_multi(g, ip, im);
-            uown += uc[ip] * phi_at(g, im, pm);
-            /* The neighbour's reference coordinates of x_p: the same in
-             * every dim but j, where x_p lies on its opposite face. */
-            double ph = 1.0;
-            for (int m = 0; m < d; ++m)
-              ph *= (m == j) ? g->L[im[m]][oj] : g->L[im[m]][pm[m]];
-            unbr += un[ip] * ph;
-          }
-        } else {
-          for (int m = 0; m < d; ++m) im[m] = pm[m];
-          uown = uc[p] * phi_at(g, pm, pm);
-          im[j] = oj;
-          double ph = 1.0;
-          for (int m = 0; m < d; ++m)
-            ph *= (m == j) ? g->L[oj][oj] : g->L[pm[m]][pm[m]];
-          unbr = un[node_linear(g, im)] * ph;
-        }
+        /* Own trace: only phi_p is nonzero at x_p. Neighbour trace: x_p
+         * lies on the neighbour's opposite face (node index oj along j), where
+         * only the neighbour's basis function of that node is nonzero. */
+        for (int m = 0; m < d; ++m) im[m] = pm[m];
+        const double uown = uc[p] * phi_at(g, pm, pm);
+        im[j] = oj;
+        double ph = 1.0;
+        for (int m = 0; m < d; ++m) ph *= (m == j) ? g->L[oj][oj] : g->L[pm[m]][pm[m]];
+        const double unbr = un[node_linear(g, im)] * ph;
         const double an = s->acell[p * d + j] * nj;
         const double ustar = (an >= 0.0) ? uown : unbr;
         const double Wf = face_weight(g, pm, j);
-        if (mode == 0) {
-          for (int64_t i = 0; i < nd; ++i) {
-            node_multi(g, i, im);
-            s->rhs[i] -= Wf * phi_at(g, im, pm) * an * ustar;
-          }
-        } else {
-          /* Only phi_p is nonzero at the node x_p. */
-          s->rhs[p] -= Wf * phi_at(g, pm, pm) * an * ustar;
-        }
+        /* Only phi_p is nonzero at the node x_p. */
+        s->rhs[p] -= Wf * phi_at(g, pm, pm) * an * ustar;
       }
     }
 
@@ -878,7 +842,7 @@ int or_apply_cells(const or_mesh *mesh, int k, const or_field *field, int mode,
         else if (mode == 2)
           eval_cell_gauss(&g, field, u, cells[t], out + t * g.nd, &s);
         else
-          eval_cell(&g, field, mode, u, cells[t], out + t * g.nd, &s);
+          eval_cell(&g, field, u, cells[t], out + t * g.nd, &s);
       }
     }
     free(s.uh);
