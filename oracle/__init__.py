@@ -69,6 +69,8 @@ def _load():
         lib.or_lsrk45_coefficients.restype = None
         lib.or_rk_steps.argtypes = [P(Mesh), ctypes.c_int, P(Field), ctypes.c_int, d,
                                     ctypes.c_int, P(d)]
+        lib.or_rk_stage.argtypes = [P(Mesh), ctypes.c_int, P(Field), ctypes.c_int, d,
+                                    ctypes.c_int, P(d), P(d), P(d)]
         lib.or_stable_dt.argtypes = [P(Mesh), ctypes.c_int, P(Field), d]
         lib.or_stable_dt.restype = d
         lib.or_init_state.argtypes = [P(Mesh), ctypes.c_int, ctypes.c_int, P(d), P(d)]
@@ -174,6 +176,16 @@ class Problem:
         if r:
             raise RuntimeError("or_rk_steps failed")
         return u
+
+    def rk_stage(self, u, du, L, dt, stage, mode=1):
+        """One RK stage in place on the float64 arrays u and du (N values
+        each; du is not read at stage 0); L is scratch of N values."""
+        for a in (u, du, L):
+            assert a.dtype == np.float64 and a.flags.c_contiguous and a.size == self.ndofs
+        r = self.lib.or_rk_stage(ctypes.byref(self.mesh), self.k, ctypes.byref(self.field),
+                                 mode, dt, stage, _dp(u), _dp(du), _dp(L))
+        if r:
+            raise RuntimeError("or_rk_stage failed")
 
     def stable_dt(self, cfl=0.2):
         return float(self.lib.or_stable_dt(ctypes.byref(self.mesh), self.k,

@@ -889,13 +889,31 @@ void or_lsrk45_coefficients(double *A, double *B, double *C) {
   C[4] = 2802321613138.0 / 2924317926251.0;
 }
 
+int or_rk_stage(const or_mesh *mesh, int k, const or_field *field, int mode, double dt,
+                int stage, double *u, double *du, double *L) {
+  or_geom g;
+  if (setup_geom(mesh, k, &g) || check_field(&g, field)) return -1;
+  if (stage < 0 || stage > 4) return -1;
+  const int64_t N = g.nd * g.ncells;
+  double A[5], B[5], C[5];
+  or_lsrk45_coefficients(A, B, C);
+  const int r = or_apply(mesh, k, field, mode, u, L);
+  if (r) return r;
+  /* A_1 = 0: the first stage does not read du (which may hold anything). */
+  const double a = A[stage], b = B[stage];
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < N; ++i) {
+    du[i] = (stage == 0 ? 0.0 : a * du[i]) + dt * L[i];
+    u[i] = u[i] + b * du[i];
+  }
+  return 0;
+}
+
 int or_rk_steps(const or_mesh *mesh, int k, const or_field *field, int mode,
                 double dt, int nsteps, double *u) {
   or_geom g;
   if (setup_geom(mesh, k, &g) || check_field(&g, field)) return -1;
   const int64_t N = g.nd * g.ncells;
-  double A[5], B[5], C[5];
-  or_lsrk45_coefficients(A, B, C);
   double *du = (double *)calloc((size_t)N, sizeof(double));
   double *L = (double *)malloc(sizeof(double) * (size_t)N);
   if (!du || !L) {
@@ -905,15 +923,7 @@ int or_rk_steps(const or_mesh *mesh, int k, const or_field *field, int mode,
   }
   int r = 0;
   for (int step = 0; step < nsteps && !r; ++step)
-    for (int st = 0; st < 5 && !r; ++st) {
-      r = or_apply(mesh, k, field, mode, u, L);
-      if (r) break;
-#pragma omp parallel for schedule(static)
-      for (int64_t i = 0; i < N; ++i) {
-        du[i] = A[st] * du[i] + dt * L[i];
-        u[i] = u[i] + B[st] * du[i];
-      }
-    }
+    for (int st = 0; st < 5 && !r; ++st) r = or_rk_stage(mesh, k, field, mode, dt, st, u, du, L);
   free(du);
   free(L);
   return r;

@@ -104,7 +104,15 @@ int or_apply(const or_mesh *mesh, int k, const or_field *field, int mode,
 /* The 2N-storage, five-stage, fourth-order RK coefficients (A, B, C). */
 void or_lsrk45_coefficients(double *A, double *B, double *C);
 
-/* nsteps steps of the low-storage RK scheme with time step dt, in place on u. */
+/* Stage `stage` (0..4) of the low-storage RK scheme (Sec. 5.4; the
+ * Carpenter-Kennedy 2N coefficients) in place: L = L(u) (scratch of N
+ * values), du <- A_s du + dt L (du is not read at stage 0, A_1 = 0),
+ * u <- u + B_s du. */
+int or_rk_stage(const or_mesh *mesh, int k, const or_field *field, int mode, double dt,
+                int stage, double *u, double *du, double *L);
+
+/* nsteps steps of the low-storage RK scheme with time step dt, in place on u
+ * (five calls of or_rk_stage per step, du starting at zero). */
 int or_rk_steps(const or_mesh *mesh, int k, const or_field *field, int mode,
                 double dt, int nsteps, double *u);
 

@@ -534,3 +534,18 @@ def test_stable_dt_phase_space_values():
     emax = 0.1 * np.abs(np.sin(2 * np.pi * xs)).max()
     want = 0.2 / (7 * (3 * 6 / (1 / 8) + 3 * emax / 1.5))
     assert abs(P.stable_dt(0.2) - want) < 1e-18
+
+
+def test_rk_stage_by_stage_equals_rk_steps():
+    # The per-stage entry (used to time one stage) composes to the same step,
+    # bitwise.
+    P = oracle.Problem(1, 1, [3, 4], [0, -6], [1, 6], 3, field="phase", sine_amp=0.2)
+    u0 = RNG.standard_normal(P.ndofs)
+    dt = P.stable_dt(0.2)
+    u = u0.copy()
+    du = np.full(P.ndofs, np.nan)  # stage 0 must not read it
+    L = np.empty(P.ndofs)
+    for _ in range(2):
+        for st in range(5):
+            P.rk_stage(u, du, L, dt, st)
+    assert np.array_equal(u, P.rk_steps(u0, dt, 2))
