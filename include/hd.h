@@ -53,9 +53,10 @@ typedef enum {
 } hd_status;
 
 /* Operator precision. HD_FP64: operator, stage increment and solution in
- * FP64. HD_FP32: operator and stage increment du in FP32 (FP32
- * accumulation); the solution u stays FP64. */
-typedef enum { HD_FP64 = 0, HD_FP32 = 1 } hd_precision;
+ * FP64 (the paper's precision throughout). HD_FP32_OP_FP64_ACC: operator and
+ * stage increment du in FP32 (FP32 accumulation of the sums); the solution
+ * u, its RK accumulation and the diagnostics stay FP64. */
+typedef enum { HD_FP64 = 0, HD_FP32_OP_FP64_ACC = 1 } hd_precision;
 
 /* Periodic Cartesian box: the tensor product of a dim_x-dimensional
  * configuration mesh and a dim_v-dimensional velocity mesh (Sec. 3.1),
@@ -119,28 +120,52 @@ typedef struct {
   int loop_dims;
 } hd_plan;
 
-/* Create a solver for `mesh` and polynomial degree `degree` (k+1 nodes per
- * dimension; degree 1..5 compiled) with precision `prec` (hd_precision).
- * The field defaults to constant zero. Allocates no device memory. */
+/* Create a solver for `mesh` (the tensor-product mesh of Sec. 3.1, eq.
+ * concept:tria:tensor) and polynomial degree `degree` (the nodal basis of
+ * Sec. 2.3: k+1 Gauss-Lobatto nodes per dimension; degree 1..5 compiled)
+ * with precision `prec` (hd_precision). The field defaults to constant
+ * zero. Allocates no device memory; *out is NULL on error.
+ * Errors: HD_ERR_INVALID (see the general conventions, or an unknown
+ * precision); HD_ERR_UNSUPPORTED for degree > 5 or an x+v split other than
+ * 1+1, 2+1, 2+2, 3+2, 3+3 (the splits of the paper's runs, Sec. 5.1). */
 hd_status hd_create(const hd_mesh *mesh, int degree, int prec, hd_solver **out);
 
-/* Destroy a solver (the caller's bound memory is not freed). NULL is a no-op. */
+/* Destroy a solver: waits for its last captured RK step still in flight,
+ * releases its host objects and graphs; the caller's bound memory is not
+ * freed. NULL is a no-op. (Bookkeeping of this interface; no passage of the
+ * paper.) */
 hd_status hd_destroy(hd_solver *s);
 
-/* Number of DoFs N = |C| (k+1)^d (Sec. 2.3, eq. dealii:totalunkonwns). */
+/* Number of DoFs N = |C| (k+1)^d, the count of eq. dealii:totalunkonwns
+ * (Sec. 2.3) for the tensor-product mesh. */
 hd_status hd_num_dofs(const hd_solver *s, int64_t *ndofs);
 
-/* Bytes of device workspace the solver needs: two FP64 solution vectors
- * (input and output of a stage), the stage increment du (FP64 or FP32),
- * the field table and reduction scratch, each 256-byte aligned. */
-hd_status hd_required_bytes(const hd_solver *s, size_t *workspace_bytes);
+/* Device memory the solver needs, in two caller-owned buffers. The
+ * low-storage RK scheme of Sec. 5.4 keeps three solution-sized vectors:
+ *  *state_bytes:     the state buffer, two FP64 solution vectors of N
+ *                    values (the input and output of a fused stage, used in
+ *                    turn; hd_state_ptr says which holds the solution);
+ *  *workspace_bytes: the workspace, the stage increment du (N values, FP64
+ *                    or FP32 by precision), the field table at the
+ *                    configuration nodes, reduction partials, and for the
+ *                    Vlasov-Poisson field or mapped cells their tables.
+ * Each section is 256-byte aligned. Errors: HD_ERR_INVALID for NULL. */
+hd_status hd_required_bytes(const hd_solver *s, size_t *state_bytes, size_t *workspace_bytes);
 
-/* Hand the solver caller-owned device memory of at least
- * hd_required_bytes(); the solution starts as zero after hd_bind. */
-hd_status hd_bind(hd_solver *s, void *workspace_dev, size_t bytes);
+/* Hand the solver its caller-owned device memory: state_dev (at least
+ * *state_bytes of hd_required_bytes) and workspace_dev (at least
+ * *workspace_bytes), both 256-byte aligned and disjoint. The library never
+ * frees them; they must outlive the solver's use. Both are cleared
+ * (synchronously) and the solution starts as zero. Re-binding drops the
+ * captured RK steps. Errors: HD_ERR_INVALID for NULL, short, misaligned or
+ * overlapping buffers; HD_ERR_HIP if clearing fails. */
+hd_status hd_bind(hd_solver *s, void *state_dev, size_t state_bytes, void *workspace_dev,
+                  size_t workspace_bytes);
 
-/* Constant advection field a (d entries) - the field of the paper's
- * performance runs (Sec. 5.1). Synchronous. */
+/* Constant advection field a (d entries) of eq. intro:advection (Sec. 1.2)
+ * - the field of the paper's performance runs (Sec. 5.1). Synchronous if
+ * bound (the table upload); before hd_bind it is kept and uploaded by
+ * hd_bind. Errors: HD_ERR_INVALID for NULL or a non-finite entry. */
 hd_status hd_set_field_constant(hd_solver *s, const double *a);
 
 /* Phase-space field a = (v, sign * E(x)) (Sec. 1.2 eq. intro:vp:simple,
@@ -151,8 +176,12 @@ hd_status hd_set_field_constant(hd_solver *s, const double *a);
  * Requires hd_bind. */
 hd_status hd_set_field_phase_space(hd_solver *s, const double *E_host, double sign);
 
-/* Phase-space field with E_j(x) = amp * sin(2 pi (x_j - lo_j)/(hi_j - lo_j))
- * at the configuration nodes. Requires hd_bind. Synchronous. */
+/* Phase-space field (as hd_set_field_phase_space) with the prescribed
+ * E_j(x) = amp * sin(2 pi (x_j - lo_j)/(hi_j - lo_j)) at the configuration
+ * nodes: the synthetic stand-in for the field of Sec. 6.1 that the
+ * benchmark workloads use. On mapped cells x is the mapped node position;
+ * hd_set_mapping recomputes the table, so the two calls may come in either
+ * order. Requires hd_bind and dim_x == dim_v. Synchronous. */
 hd_status hd_set_field_sine(hd_solver *s, double amp, double sign);
 
 /* Vlasov-Poisson field (Sec. 6, eq. vp:close): electrons on a neutralizing
@@ -219,20 +248,33 @@ hd_status hd_set_mapping(hd_solver *s, double eps);
  * A no-op for prescribed fields. Requires hd_bind. */
 hd_status hd_compute_field(hd_solver *s, hd_stream stream);
 
-/* Copy a canonical FP64 state (host or device pointer) into the solution. */
+/* Copy a canonical FP64 state (N values; host or device pointer, as
+ * u_is_device says) into the current solution buffer, on `stream`
+ * (asynchronous; a host pointer must stay valid until the stream reaches
+ * the copy). The nodal values are the coefficients of the nodal basis of
+ * Sec. 2.3. Requires hd_bind. Errors: HD_ERR_INVALID for NULL or unbound. */
 hd_status hd_set_state(hd_solver *s, const double *u, int u_is_device, hd_stream stream);
 
-/* Nodal interpolation of an initial state on the device.
+/* Nodal interpolation (values at the nodes of Sec. 2.3; the paper does not
+ * say how initial data enter, this library interpolates) of an initial
+ * state on the device, into the current solution buffer, on `stream`:
  *  kind 0: prod_j sin(2 pi (x_j - lo_j)/(hi_j - lo_j));
  *  kind 1: (1 + params[0] cos(2 pi (x_1 - lo_1)/(hi_1 - lo_1)))
- *          * (2 pi)^(-dv/2) exp(-|v|^2/2). */
+ *          * (2 pi)^(-dv/2) exp(-|v|^2/2), the perturbed Maxwellian of the
+ *          Landau-damping setting of Sec. 6.2.
+ * Node positions follow the mapping on mapped cells. Requires hd_bind.
+ * Errors: HD_ERR_INVALID for an unknown kind or unbound solver. */
 hd_status hd_init_state(hd_solver *s, int kind, const double *params, hd_stream stream);
 
-/* Device pointer to the current FP64 solution (N doubles, canonical). It
- * moves between the two solution buffers after each RK stage. */
+/* Device pointer to the current FP64 solution (N doubles, canonical),
+ * inside the bound state buffer. It moves between the two solution vectors
+ * after each RK stage (the ping-pong of the three-vector scheme, Sec. 5.4).
+ * Requires hd_bind. */
 hd_status hd_state_ptr(const hd_solver *s, void **dev_ptr);
 
-/* Copy the current solution to host memory (N doubles). Synchronizes. */
+/* Copy the current solution (canonical layout, Sec. 3.2 enumeration) to
+ * host memory (N doubles) after the work queued on `stream`. Synchronizes
+ * the stream. Requires hd_bind. */
 hd_status hd_get_state(const hd_solver *s, double *u_host, hd_stream stream);
 
 /* out = M^{-1} A(in): the element-centric evaluation of Algorithm 2 (cell
@@ -241,9 +283,14 @@ hd_status hd_get_state(const hd_solver *s, double *u_host, hd_stream stream);
  * out: N values on the device, FP64 for HD_FP64 and FP32 for HD_FP32. */
 hd_status hd_apply(hd_solver *s, const double *in_dev, void *out_dev, hd_stream stream);
 
-/* dt = cfl / ((2k+1) sum_j max|a_j| / h_j) for the current field. For the
- * Vlasov-Poisson field, E is that of the current state, computed on the
- * null stream (which waits for blocking streams) before this returns. */
+/* dt = cfl / ((2k+1) sum_j max|a_j| / h_j) for the current field. The
+ * paper fixes no time-step rule (Sec. 5.4 names the scheme only); this is
+ * the library's reading: the usual DG advective limit with the maximum of
+ * |a_j| over the nodes, max|v_j| over the velocity nodes for a_{x_j} and
+ * max|E_j| over the table for a_{v_j}. It ignores the mapping of mapped
+ * cells. For the Vlasov-Poisson field, E is that of the current state,
+ * computed on the null stream (which waits for blocking streams) before
+ * this returns. Errors: HD_ERR_INVALID for cfl <= 0 or an all-zero field. */
 hd_status hd_stable_dt(const hd_solver *s, double cfl, double *dt);
 
 /* One stage (stage = 0..4) of the low-storage RK scheme (Sec. 5.4), fused
@@ -258,19 +305,34 @@ hd_status hd_rk_stage(hd_solver *s, int stage, double dt, hd_stream stream);
  * captured per (dt, solution buffer parity). */
 hd_status hd_rk_step(hd_solver *s, double dt, int nsteps, hd_stream stream);
 
-/* mass = sum_i W_i u_i, energy = sum_i W_i u_i^2 with W_i = prod_j h_j w_{i_j},
- * in FP64 with a fixed reduction order (bitwise reproducible). Synchronizes. */
+/* The discrete mass and L2 energy of the current solution, integrated with
+ * the Gauss-Lobatto quadrature of Sec. 2.5 (the diagonal mass matrix of the
+ * collocated basis, Sec. 1.3): mass = sum_i W_i u_i, energy =
+ * sum_i W_i u_i^2 with W_i = prod_j h_j w_{i_j} (times |J| at the node on
+ * mapped cells). The upwind scheme conserves the first and does not
+ * increase the second (Sec. 1.3). FP64 with a fixed reduction order
+ * (bitwise reproducible); the partial sums live in the workspace.
+ * Synchronizes `stream`. Requires hd_bind. */
 hd_status hd_diagnostics(const hd_solver *s, double *mass, double *energy, hd_stream stream);
 
-/* Read / override the stage-kernel launch plan. */
+/* Read / override the stage-kernel launch plan (hd_plan above). Plans
+ * change how the kernels map cells and nodes onto the GPU, never the
+ * result beyond rounding order; they have no counterpart in the paper,
+ * whose CPU code fixes its vectorization over cells (Sec. 4). hd_set_plan
+ * returns HD_ERR_INVALID (with the reason) for a plan that does not fit
+ * the limits or has no compiled kernel, and drops the captured steps. */
 hd_status hd_get_plan(const hd_solver *s, hd_plan *plan);
 hd_status hd_set_plan(hd_solver *s, const hd_plan *plan);
 
 /* dst[i] = src[i], i < n, on the stream: a plain streaming copy used to
- * measure achievable HBM bandwidth and to calibrate byte counters. */
+ * measure achievable HBM bandwidth and to calibrate byte counters (a
+ * measurement aid; no passage of the paper). src and dst: device, 16-byte
+ * aligned, not overlapping. */
 hd_status hd_stream_copy(const double *src, double *dst, size_t n, hd_stream stream);
 
-/* Message of the last error on this thread ("" if none). */
+/* Message of the last error on this thread ("" if none); the pointer stays
+ * valid until the thread's next failing call. (Bookkeeping of this
+ * interface; no passage of the paper.) */
 const char *hd_last_error(void);
 
 /* Batched stepping of many independent solves (Sec. 5.4 time stepping of

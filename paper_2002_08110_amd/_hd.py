@@ -17,7 +17,7 @@ HD_ERR_OOM = -3
 HD_ERR_HIP = -4
 HD_ERR_STATE = -5
 HD_FP64 = 0
-HD_FP32 = 1
+HD_FP32_OP_FP64_ACC = 1
 
 # Every symbol include/hd.h declares.
 SYMBOLS = (
@@ -76,8 +76,8 @@ def load():
         "hd_create": ([P(hd_mesh), i, i, P(vp)], st),
         "hd_destroy": ([vp], st),
         "hd_num_dofs": ([vp, P(ctypes.c_int64)], st),
-        "hd_required_bytes": ([vp, P(ctypes.c_size_t)], st),
-        "hd_bind": ([vp, vp, ctypes.c_size_t], st),
+        "hd_required_bytes": ([vp, P(ctypes.c_size_t), P(ctypes.c_size_t)], st),
+        "hd_bind": ([vp, vp, ctypes.c_size_t, vp, ctypes.c_size_t], st),
         "hd_set_field_constant": ([vp, P(d)], st),
         "hd_set_field_phase_space": ([vp, P(d), d], st),
         "hd_set_field_sine": ([vp, d, d], st),

@@ -39,7 +39,18 @@ struct Cached {
   StepKey key;
   hipGraphExec_t exec = nullptr;
   uint64_t used = 0;
+  // Recorded after each replay: the exec is destroyed only after it.
+  hipEvent_t done = nullptr;
+  bool pending = false;
 };
+
+// Destroy a cached step graph once its last replay has finished.
+void release(Cached &c) {
+  if (c.pending && c.done) hipEventSynchronize(c.done);
+  c.pending = false;
+  if (c.exec) hipGraphExecDestroy(c.exec);
+  c.exec = nullptr;
+}
 
 }  // namespace
 
@@ -108,8 +119,10 @@ hd_status capture(hd_batch *b, const StepKey &key, hipGraphExec_t *out) {
 
 void destroy_batch(hd_batch *b) {
   if (!b) return;
-  for (Cached &c : b->cache)
-    if (c.exec) hipGraphExecDestroy(c.exec);
+  for (Cached &c : b->cache) {
+    release(c);
+    if (c.done) hipEventDestroy(c.done);
+  }
   for (hipEvent_t e : b->ev)
     if (e) hipEventDestroy(e);
   for (hipStream_t s : b->side)
@@ -122,6 +135,7 @@ hd_status init_batch(hd_batch *b) {
   HD_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
   for (hipStream_t &s : b->side) HD_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
   for (hipEvent_t &e : b->ev) HD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  for (Cached &c : b->cache) HD_HIP(hipEventCreateWithFlags(&c.done, hipEventDisableTiming));
   return HD_OK;
 }
 
@@ -135,7 +149,7 @@ hd_status hd_batch_create(hd_solver *const *solvers, int n, hd_batch **out) {
   if (n < 1 || n > kMaxBatch) return fail(HD_ERR_INVALID, "batch size must be 1..1024");
   for (int i = 0; i < n; ++i) {
     hd_solver *s = solvers[i];
-    if (!s || !s->ws) return fail(HD_ERR_INVALID, "every batched solver must be bound (hd_bind)");
+    if (!s || !s->bound()) return fail(HD_ERR_INVALID, "every batched solver must be bound (hd_bind)");
     for (int j = 0; j < i; ++j)
       if (solvers[j] == s) return fail(HD_ERR_INVALID, "a solver appears twice in the batch");
   }
@@ -171,7 +185,7 @@ hd_status hd_batch_step(hd_batch *b, const double *dt, const int *active, hd_str
     any = true;
     if (!(dt[i] == dt[i] && dt[i] > -1e300 && dt[i] < 1e300))
       return fail(HD_ERR_INVALID, "dt must be finite");
-    if (!b->solvers[i]->ws) return fail(HD_ERR_INVALID, "a batched solver lost its workspace");
+    if (!b->solvers[i]->bound()) return fail(HD_ERR_INVALID, "a batched solver lost its memory");
     key.par[i] = b->solvers[i]->cur;
     key.dt[i] = dt[i];
     key.version[i] = b->solvers[i]->version;
@@ -183,16 +197,15 @@ hd_status hd_batch_step(hd_batch *b, const double *dt, const int *active, hd_str
   if (!hit) {
     // Replace the least recently used of the two cached steps.
     hit = b->cache[0].used <= b->cache[1].used ? &b->cache[0] : &b->cache[1];
-    if (hit->exec) {
-      hipGraphExecDestroy(hit->exec);
-      hit->exec = nullptr;
-    }
+    release(*hit);
     hd_status r = capture(b, key, &hit->exec);
     if (r != HD_OK) return r;
     hit->key = key;
   }
   hit->used = ++b->clock;
   HD_HIP(hipGraphLaunch(hit->exec, (hipStream_t)stream));
+  HD_HIP(hipEventRecord(hit->done, (hipStream_t)stream));
+  hit->pending = true;
   for (int i = 0; i < n; ++i)
     if (key.active[i]) b->solvers[i]->cur ^= 1;  // five stages: the other buffer
   return HD_OK;

@@ -25,9 +25,18 @@ struct hd_solver {
   double esign = 1.0;
   std::vector<double> E_host;  // E at x-nodes (phase-space field)
   int64_t nE = 0;              // entries of the E table
-  // Workspace layout (offsets into the caller's buffer).
-  size_t off_u[2] = {0, 0}, off_du = 0, off_E = 0, off_part = 0, total = 0;
+  // The prescribed sine field (hd_set_field_sine): its amplitude and sign,
+  // kept so that a later mapping recomputes the table at the mapped nodes.
+  bool sine = false;
+  double sine_amp = 0.0, sine_sign = 1.0;
+  // Caller-owned device memory: the state buffer holds the two FP64
+  // solution vectors (offsets off_u), the workspace everything else
+  // (offsets below), each section 256-byte aligned.
+  size_t off_u[2] = {0, 0}, state_total = 0;
+  size_t off_du = 0, off_E = 0, off_part = 0, total = 0;
+  char *state = nullptr;
   char *ws = nullptr;
+  bool bound() const { return state != nullptr && ws != nullptr; }
   int cur = 0;  // which of the two solution buffers holds the solution
   hd_plan plan{};
   // Captured RK steps (index = solution buffer parity at the start).
@@ -35,6 +44,10 @@ struct hd_solver {
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   double gdt = 0.0;
   bool gvalid = false;
+  // Recorded after the last replay of a captured step: a graph is destroyed
+  // only once its launches have finished.
+  hipEvent_t gdone = nullptr;
+  bool gpending = false;
   uint64_t version = 0;  // bumped when the plan, field or memory changes
   // Quadrature: 0 Gauss-Lobatto collocation, 1 Gauss-Legendre (k+1 points).
   int quad = 0;
@@ -55,7 +68,7 @@ struct hd_solver {
   size_t vp_mom_bytes = 0;
   const double *vp_mom_src = nullptr;
 
-  double *u(int i) const { return reinterpret_cast<double *>(ws + off_u[i]); }
+  double *u(int i) const { return reinterpret_cast<double *>(state + off_u[i]); }
   void *du() const { return ws + off_du; }
   void *E() const { return ws + off_E; }
   double *part() const { return reinterpret_cast<double *>(ws + off_part); }
@@ -67,7 +80,7 @@ struct hd_solver {
   double2 *vp_mats() const { return reinterpret_cast<double2 *>(ws + off_vp_mats); }
   double *vp_mom() const { return reinterpret_cast<double *>(ws + off_vp_mom); }
   double *xmetric() const { return reinterpret_cast<double *>(ws + off_xmetric); }
-  size_t psize() const { return prec == HD_FP32 ? sizeof(float) : sizeof(double); }
+  size_t psize() const { return prec == HD_FP32_OP_FP64_ACC ? sizeof(float) : sizeof(double); }
 };
 
 #define HD_HIP(expr)                                                                         \

@@ -176,7 +176,7 @@ hd_plan default_plan(const hd_solver *s) {
   // helps both precisions, keeping the FP64 input in registers helps FP32.
   // The generic kernel streams them once the vectors outgrow the caches
   // (the autotuner picked streaming for most (d, k) at 1.5e8 DoFs).
-  if (p.kernel == 1) p.options = s->prec == HD_FP32 ? 3 : 1;
+  if (p.kernel == 1) p.options = s->prec == HD_FP32_OP_FP64_ACC ? 3 : 1;
   else p.options = s->ndofs >= (int64_t(1) << 25) ? 1 : 0;
   // Cell order of the 6D degree-3 kernel (measured on MI355X over 4^6 to
   // 9^6 and mixed meshes, with data of full entropy): in FP64 from about
@@ -195,19 +195,19 @@ hd::LaunchShape hd::rt::shape_of(const hd_solver *s) {
   if (hd::rt::k3g_used(s)) {
     ls.grid = (unsigned)s->ncells;
     ls.block = 256;
-    ls.shmem = s->prec == HD_FP32 ? hd::k3g_lds_bytes<float>() : hd::k3g_lds_bytes<double>();
+    ls.shmem = s->prec == HD_FP32_OP_FP64_ACC ? hd::k3g_lds_bytes<float>() : hd::k3g_lds_bytes<double>();
     return ls;
   }
   if (hd::rt::k3m_used(s)) {
     ls.grid = (unsigned)s->ncells;
     ls.block = 256;
-    ls.shmem = s->prec == HD_FP32 ? hd::k3m_lds_bytes<float>() : hd::k3m_lds_bytes<double>();
+    ls.shmem = s->prec == HD_FP32_OP_FP64_ACC ? hd::k3m_lds_bytes<float>() : hd::k3m_lds_bytes<double>();
     return ls;
   }
   if (hd::rt::k3mg_used(s)) {
     ls.grid = (unsigned)s->ncells;
     ls.block = 256;
-    ls.shmem = s->prec == HD_FP32 ? hd::k3mg_lds_bytes<float>() : hd::k3mg_lds_bytes<double>();
+    ls.shmem = s->prec == HD_FP32_OP_FP64_ACC ? hd::k3mg_lds_bytes<float>() : hd::k3mg_lds_bytes<double>();
     return ls;
   }
   if (s->quad == 1 || s->mapped()) {
@@ -219,7 +219,7 @@ hd::LaunchShape hd::rt::shape_of(const hd_solver *s) {
   if (s->plan.kernel == 1) {
     ls.grid = (unsigned)s->ncells;
     ls.block = 256;
-    ls.shmem = s->prec == HD_FP32 ? hd::k3_lds_bytes<float>() : hd::k3_lds_bytes<double>();
+    ls.shmem = s->prec == HD_FP32_OP_FP64_ACC ? hd::k3_lds_bytes<float>() : hd::k3_lds_bytes<double>();
     return ls;
   }
   const int sd = s->plan.split_dims;
@@ -245,7 +245,7 @@ namespace hd {
 namespace rt {
 
 const void *stage_entry(const hd_solver *s, int k3_role) {
-  const bool f32 = s->prec == HD_FP32;
+  const bool f32 = s->prec == HD_FP32_OP_FP64_ACC;
   if (k3g_used(s)) return hd::stage_k3g_entry(f32);
   if (k3m_used(s)) return hd::stage_k3m_entry(f32);
   if (k3mg_used(s)) return hd::stage_k3mg_entry(f32);
@@ -381,7 +381,7 @@ hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, in
   // the late-increment variant serves the last stage (FP64) or every later
   // stage (FP32), where it measured faster than holding the increment
   // through the sweeps.
-  const bool f32 = s->prec == HD_FP32;
+  const bool f32 = s->prec == HD_FP32_OP_FP64_ACC;
   const int k3_role = mode != 1 ? 0 : (!prm.read_du ? 1 : (f32 || !prm.write_du ? 2 : 0));
   // The plan's cell order governs the general variant. The FP64 first-stage
   // and late-increment variants measured faster with one slab per XCD at 8^6
@@ -454,13 +454,16 @@ hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, in
 hd_status enqueue_stage(hd_solver *s, int stage, double dt, hipStream_t st) {
   const double *in = s->u(s->cur);
   double *out = s->u(1 - s->cur);
-  hd_status r = s->prec == HD_FP32 ? launch_op<float>(s, in, nullptr, out, 1, stage, dt, st)
+  hd_status r = s->prec == HD_FP32_OP_FP64_ACC ? launch_op<float>(s, in, nullptr, out, 1, stage, dt, st)
                                    : launch_op<double>(s, in, nullptr, out, 1, stage, dt, st);
   if (r == HD_OK) s->cur = 1 - s->cur;
   return r;
 }
 
 void drop_graphs(hd_solver *s) {
+  // A replay may still run on the caller's stream: wait for it first.
+  if (s->gpending && s->gdone) hipEventSynchronize(s->gdone);
+  s->gpending = false;
   for (int i = 0; i < 2; ++i)
     if (s->gexec[i]) {
       hipGraphExecDestroy(s->gexec[i]);
@@ -478,7 +481,7 @@ void changed(hd_solver *s) {
 
 hd_status check_bound(const hd_solver *s) {
   if (!s) return fail(HD_ERR_INVALID, "solver is NULL");
-  if (!s->ws) return fail(HD_ERR_INVALID, "solver has no bound workspace (call hd_bind)");
+  if (!s->bound()) return fail(HD_ERR_INVALID, "solver has no bound memory (call hd_bind)");
   return HD_OK;
 }
 
@@ -649,7 +652,7 @@ GeomArgs geom_of(const hd_solver *s) {
 // Metric of the mapped x-cells at the current quadrature points (layout of
 // hd::gauss_metric_elems), uploaded to the device table.
 hd_status upload_metric(hd_solver *s) {
-  if (!s->mapped() || !s->ws) return HD_OK;
+  if (!s->mapped() || !s->bound()) return HD_OK;
   const int n = s->n, dx = s->dx;
   const double *pt = s->quad == 1 ? s->gtab.g : s->tab.xi;
   int64_t nxc = 1, nxn = 1;
@@ -741,7 +744,7 @@ hd_status upload_E(hd_solver *s) {
     s->E_host.assign(n, 0.0);
     for (size_t i = 0; i < n; ++i) s->E_host[i] = s->a_const[s->dx + (int)(i % (size_t)s->dx)];
   }
-  if (s->prec == HD_FP32) {
+  if (s->prec == HD_FP32_OP_FP64_ACC) {
     std::vector<float> tmp(s->E_host.begin(), s->E_host.end());
     HD_HIP(hipMemcpy(s->E(), tmp.data(), n * sizeof(float), hipMemcpyHostToDevice));
   } else {
@@ -773,7 +776,7 @@ __global__ void stream_copy_tail(const double *src, double *dst, size_t begin, s
 hd_status hd::rt::enqueue_step(hd_solver *s, int par, double dt, hipStream_t st) {
   for (int stage = 0; stage < 5; ++stage, par = 1 - par) {
     const hd_status r =
-        s->prec == HD_FP32 ? launch_op<float>(s, s->u(par), nullptr, s->u(1 - par), 1, stage, dt, st)
+        s->prec == HD_FP32_OP_FP64_ACC ? launch_op<float>(s, s->u(par), nullptr, s->u(1 - par), 1, stage, dt, st)
                            : launch_op<double>(s, s->u(par), nullptr, s->u(1 - par), 1, stage, dt, st);
     if (r != HD_OK) return r;
   }
@@ -790,7 +793,7 @@ hd_status hd_create(const hd_mesh *mesh, int degree, int prec, hd_solver **out) 
   if (mesh->dim_x < 1 || mesh->dim_x > 3 || mesh->dim_v < 1 || mesh->dim_v > 3)
     return fail(HD_ERR_INVALID, "dim_x and dim_v must be in 1..3");
   if (degree < 1) return fail(HD_ERR_INVALID, "degree must be >= 1");
-  if (prec != HD_FP64 && prec != HD_FP32) return fail(HD_ERR_INVALID, "unknown precision");
+  if (prec != HD_FP64 && prec != HD_FP32_OP_FP64_ACC) return fail(HD_ERR_INVALID, "unknown precision");
   const int d = mesh->dim_x + mesh->dim_v;
   long double cells_total = 1.0L;
   for (int j = 0; j < d; ++j) {
@@ -839,6 +842,8 @@ hd_status hd_create(const hd_mesh *mesh, int degree, int prec, hd_solver **out) 
   off = align_up(off + N * sizeof(double));
   s->off_u[1] = off;
   off = align_up(off + N * sizeof(double));
+  s->state_total = off;
+  off = 0;
   s->off_du = off;
   off = align_up(off + N * s->psize());
   s->off_E = off;
@@ -857,6 +862,7 @@ hd_status hd_create(const hd_mesh *mesh, int degree, int prec, hd_solver **out) 
 hd_status hd_destroy(hd_solver *s) {
   if (!s) return HD_OK;
   drop_graphs(s);
+  if (s->gdone) hipEventDestroy(s->gdone);
   if (s->cap) hipStreamDestroy(s->cap);
   delete s;
   return HD_OK;
@@ -868,20 +874,31 @@ hd_status hd_num_dofs(const hd_solver *s, int64_t *ndofs) {
   return HD_OK;
 }
 
-hd_status hd_required_bytes(const hd_solver *s, size_t *bytes) {
-  if (!s || !bytes) return fail(HD_ERR_INVALID, "NULL argument");
-  *bytes = s->total;
+hd_status hd_required_bytes(const hd_solver *s, size_t *state_bytes, size_t *workspace_bytes) {
+  if (!s || !state_bytes || !workspace_bytes) return fail(HD_ERR_INVALID, "NULL argument");
+  *state_bytes = s->state_total;
+  *workspace_bytes = s->total;
   return HD_OK;
 }
 
-hd_status hd_bind(hd_solver *s, void *ws, size_t bytes) {
-  if (!s || !ws) return fail(HD_ERR_INVALID, "NULL argument");
-  if (bytes < s->total) return fail(HD_ERR_INVALID, "workspace smaller than hd_required_bytes");
-  if (reinterpret_cast<uintptr_t>(ws) % kAlign)
-    return fail(HD_ERR_INVALID, "workspace must be 256-byte aligned");
+hd_status hd_bind(hd_solver *s, void *state_dev, size_t state_bytes, void *workspace_dev,
+                  size_t workspace_bytes) {
+  if (!s || !state_dev || !workspace_dev) return fail(HD_ERR_INVALID, "NULL argument");
+  if (state_bytes < s->state_total)
+    return fail(HD_ERR_INVALID, "state buffer smaller than hd_required_bytes");
+  if (workspace_bytes < s->total)
+    return fail(HD_ERR_INVALID, "workspace smaller than hd_required_bytes");
+  if ((reinterpret_cast<uintptr_t>(state_dev) | reinterpret_cast<uintptr_t>(workspace_dev)) % kAlign)
+    return fail(HD_ERR_INVALID, "state and workspace must be 256-byte aligned");
+  const char *sb = reinterpret_cast<const char *>(state_dev);
+  const char *wb = reinterpret_cast<const char *>(workspace_dev);
+  if (sb < wb + s->total && wb < sb + s->state_total)
+    return fail(HD_ERR_INVALID, "state and workspace must not overlap");
   changed(s);
-  s->ws = reinterpret_cast<char *>(ws);
+  s->state = reinterpret_cast<char *>(state_dev);
+  s->ws = reinterpret_cast<char *>(workspace_dev);
   s->cur = 0;
+  HD_HIP(hipMemset(s->state, 0, s->state_total));
   HD_HIP(hipMemset(s->ws, 0, s->total));
   hd_status r = upload_metric(s);
   if (r) return r;
@@ -893,28 +910,30 @@ hd_status hd_set_field_constant(hd_solver *s, const double *a) {
   for (int j = 0; j < s->d; ++j)
     if (!std::isfinite(a[j])) return fail(HD_ERR_INVALID, "field must be finite");
   s->field_kind = 0;
+  s->sine = false;
   for (int j = 0; j < 6; ++j) s->a_const[j] = j < s->d ? a[j] : 0.0;
   changed(s);
-  if (s->ws) return upload_E(s);
+  if (s->bound()) return upload_E(s);
   return HD_OK;
 }
 
-hd_status hd_set_field_phase_space(hd_solver *s, const double *E_host, double sign) {
-  if (!s || !E_host) return fail(HD_ERR_INVALID, "NULL argument");
-  if (s->dx != s->dv) return fail(HD_ERR_INVALID, "phase-space field needs dim_x == dim_v");
-  hd_status r = check_bound(s);
-  if (r) return r;
+}  // extern "C"
+
+namespace {
+
+// The phase-space field with table E (nE values) and sign; the caller has
+// checked the solver.
+hd_status set_phase_table(hd_solver *s, const double *E_host, double sign) {
+  for (int64_t i = 0; i < s->nE; ++i)
+    if (!std::isfinite(E_host[i])) return fail(HD_ERR_INVALID, "E must be finite");
   s->E_host.assign(E_host, E_host + s->nE);
-  for (double v : s->E_host)
-    if (!std::isfinite(v)) return fail(HD_ERR_INVALID, "E must be finite");
   s->field_kind = 1;
   s->esign = sign;
   return upload_E(s);
 }
 
-hd_status hd_set_field_sine(hd_solver *s, double amp, double sign) {
-  if (!s) return fail(HD_ERR_INVALID, "NULL argument");
-  if (s->dx != s->dv) return fail(HD_ERR_INVALID, "phase-space field needs dim_x == dim_v");
+// E_j = amp sin(2 pi (x_j - lo_j) / L_j) at the (mapped) configuration nodes.
+std::vector<double> sine_table(const hd_solver *s, double amp) {
   std::vector<double> E((size_t)s->nE);
   int64_t nxc = 1, nxn = 1;
   for (int j = 0; j < s->dx; ++j) {
@@ -946,7 +965,35 @@ hd_status hd_set_field_sine(hd_solver *s, double amp, double sign) {
             amp * std::sin(two_pi * (x - s->mesh.lo[j]) / (s->mesh.hi[j] - s->mesh.lo[j]));
       }
     }
-  return hd_set_field_phase_space(s, E.data(), sign);
+  return E;
+}
+
+}  // namespace
+
+extern "C" {
+
+hd_status hd_set_field_phase_space(hd_solver *s, const double *E_host, double sign) {
+  if (!s || !E_host) return fail(HD_ERR_INVALID, "NULL argument");
+  if (s->dx != s->dv) return fail(HD_ERR_INVALID, "phase-space field needs dim_x == dim_v");
+  hd_status r = check_bound(s);
+  if (r) return r;
+  s->sine = false;
+  return set_phase_table(s, E_host, sign);
+}
+
+hd_status hd_set_field_sine(hd_solver *s, double amp, double sign) {
+  if (!s) return fail(HD_ERR_INVALID, "NULL argument");
+  if (s->dx != s->dv) return fail(HD_ERR_INVALID, "phase-space field needs dim_x == dim_v");
+  hd_status r = check_bound(s);
+  if (r) return r;
+  if (!std::isfinite(amp) || !std::isfinite(sign)) return fail(HD_ERR_INVALID, "amp and sign must be finite");
+  const std::vector<double> E = sine_table(s, amp);
+  r = set_phase_table(s, E.data(), sign);
+  if (r) return r;
+  s->sine = true;
+  s->sine_amp = amp;
+  s->sine_sign = sign;
+  return HD_OK;
 }
 
 hd_status hd_set_field_vlasov_poisson(hd_solver *s, int modes) {
@@ -958,6 +1005,7 @@ hd_status hd_set_field_vlasov_poisson(hd_solver *s, int modes) {
   if (modes < 1 || modes > hd::rt::kVpMaxModes)
     return fail(HD_ERR_INVALID, "modes must be 1.." + std::to_string(hd::rt::kVpMaxModes));
   s->field_kind = 2;
+  s->sine = false;
   s->esign = -1.0;
   s->vp_modes = modes;
   return upload_E(s);
@@ -969,7 +1017,7 @@ hd_status hd_set_quadrature(hd_solver *s, int quadrature) {
     return fail(HD_ERR_INVALID, "quadrature must be 0 (Gauss-Lobatto) or 1 (Gauss-Legendre)");
   if (quadrature == 1) {
     if (!s->gtab_ok) return fail(HD_ERR_INVALID, "Gauss-Legendre table construction failed");
-    if (!hd::stage_gauss_entry(s->d, s->n, s->prec == HD_FP32))
+    if (!hd::stage_gauss_entry(s->d, s->n, s->prec == HD_FP32_OP_FP64_ACC))
       return fail(HD_ERR_UNSUPPORTED,
                   "the Gauss-Legendre kernel holds two cell-sized arrays and a face layer in "
                   "LDS: this "
@@ -985,7 +1033,7 @@ hd_status hd_set_mapping(hd_solver *s, double eps) {
   if (!(std::fabs(eps) <= 0.05)) return fail(HD_ERR_INVALID, "|eps| must be at most 0.05");
   if (eps != 0.0 && s->field_kind == 2)
     return fail(HD_ERR_UNSUPPORTED, "the Vlasov-Poisson field needs Cartesian cells");
-  if (eps != 0.0 && !hd::stage_gauss_entry(s->d, s->n, s->prec == HD_FP32, true))
+  if (eps != 0.0 && !hd::stage_gauss_entry(s->d, s->n, s->prec == HD_FP32_OP_FP64_ACC, true))
     return fail(HD_ERR_UNSUPPORTED,
                 "the mapped-cell kernel holds two cell-sized arrays and a face layer in LDS: "
                 "this (d, degree, precision) exceeds 160 KiB or is not compiled");
@@ -993,7 +1041,15 @@ hd_status hd_set_mapping(hd_solver *s, double eps) {
   s->map_eps = eps;
   changed(s);
   hd_status r = upload_metric(s);
-  if (r) s->map_eps = old;
+  if (r) {
+    s->map_eps = old;
+    return r;
+  }
+  // The sine field lives at the node positions, which moved.
+  if (s->sine && s->field_kind == 1 && s->bound()) {
+    const std::vector<double> E = sine_table(s, s->sine_amp);
+    r = set_phase_table(s, E.data(), s->sine_sign);
+  }
   return r;
 }
 
@@ -1015,7 +1071,7 @@ hd_status hd_get_field(hd_solver *s, double *E_host, hd_stream stream) {
     if (r) return r;
   }
   const size_t n = (size_t)s->nE;
-  if (s->prec == HD_FP32) {
+  if (s->prec == HD_FP32_OP_FP64_ACC) {
     std::vector<float> tmp(n);
     HD_HIP(hipMemcpyAsync(tmp.data(), s->E(), n * sizeof(float), hipMemcpyDeviceToHost, st));
     HD_HIP(hipStreamSynchronize(st));
@@ -1078,7 +1134,7 @@ hd_status hd_apply(hd_solver *s, const double *in, void *out, hd_stream stream) 
   const char *ob = reinterpret_cast<const char *>(out);
   const size_t ibytes = sizeof(double) * (size_t)s->ndofs, obytes = s->psize() * (size_t)s->ndofs;
   if (ib < ob + obytes && ob < ib + ibytes) return fail(HD_ERR_INVALID, "in and out must not overlap");
-  return s->prec == HD_FP32 ? launch_op<float>(s, in, out, nullptr, 0, 0, 0.0, (hipStream_t)stream)
+  return s->prec == HD_FP32_OP_FP64_ACC ? launch_op<float>(s, in, out, nullptr, 0, 0, 0.0, (hipStream_t)stream)
                             : launch_op<double>(s, in, out, nullptr, 0, 0, 0.0, (hipStream_t)stream);
 }
 
@@ -1160,10 +1216,13 @@ hd_status hd_rk_step(hd_solver *s, double dt, int nsteps, hd_stream stream) {
     s->gdt = dt;
     s->gvalid = true;
   }
+  if (!s->gdone) HD_HIP(hipEventCreateWithFlags(&s->gdone, hipEventDisableTiming));
   for (int i = 0; i < nsteps; ++i) {
     HD_HIP(hipGraphLaunch(s->gexec[s->cur], (hipStream_t)stream));
     s->cur = 1 - s->cur;  // five stages: the solution ends in the other buffer
   }
+  HD_HIP(hipEventRecord(s->gdone, (hipStream_t)stream));
+  s->gpending = true;
   return HD_OK;
 }
 

@@ -326,7 +326,7 @@ hd_status vp_enqueue(hd_solver *s, const double *u, hipStream_t st, bool moments
       dst = other;
       other = t;
     }
-    if (s->prec == HD_FP32)
+    if (s->prec == HD_FP32_OP_FP64_ACC)
       hipLaunchKernelGGL(vp_scatter<float>, dim3(blocks_for(g.npts)), dim3(kVpThreads), 0, st, g,
                          src, c, reinterpret_cast<float *>(s->E()));
     else

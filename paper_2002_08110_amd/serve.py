@@ -16,8 +16,14 @@ once.
 The loop is host bookkeeping only: every stage runs in the library's
 kernels.
 
+A request that can never run is rejected with a status and the server
+goes on: its footprint exceeds the whole budget (status "rejected", code
+HD_ERR_OOM), or the library refuses it at set-up (code: the library's
+status). Every other request ends with status "done".
+
 Times are wall-clock seconds from the start of the run; latency is
 completion minus arrival, service time completion minus admission.
+Latency statistics cover the completed requests.
 """
 from __future__ import annotations
 
@@ -27,9 +33,9 @@ import time
 import numpy as np
 import torch
 
+from . import _hd
 from .solver import Batch, Solver
 
-_ALIGN = 256
 
 
 @dataclasses.dataclass
@@ -44,6 +50,9 @@ class Result:
     mass: float = float("nan")
     energy: float = float("nan")
     state: np.ndarray | None = None
+    status: str = "pending"   # "done" or "rejected"
+    code: int = 0             # hd_status of a rejection (0 otherwise)
+    reason: str = ""
 
     @property
     def latency(self):
@@ -75,7 +84,7 @@ def setup(s, case):
 
 def footprint(case, precision):
     s = make_solver(case, precision, tuned=False, bind=False)
-    b = s.workspace_bytes + _ALIGN
+    b = s.device_bytes
     s.close()
     return b
 
@@ -108,10 +117,6 @@ def serve(requests, precision="fp32", budget=None, batched=True, keep_states=Fal
     results = {r.rid: Result(r.rid, r.arrival * time_scale, ndofs=r.case.ndofs,
                              steps=r.case.steps, footprint=footprint(r.case, precision))
                for r in reqs}
-    for r in reqs:
-        if results[r.rid].footprint > budget:
-            raise ValueError("request %d needs %d bytes, more than the budget %d"
-                             % (r.rid, results[r.rid].footprint, budget))
     waiting, running = [], []
     nxt = 0
     used = 0
@@ -125,11 +130,24 @@ def serve(requests, precision="fp32", budget=None, batched=True, keep_states=Fal
     def now():
         return time.perf_counter() - t0
 
+    def reject(r, code, reason):
+        res = results[r.rid]
+        res.status, res.code, res.reason = "rejected", code, reason
+        res.completed = now()
+        if log:
+            log("request %d rejected (status %d): %s" % (r.rid, code, reason))
+
     while nxt < len(reqs) or waiting or running:
         t = now()
         while nxt < len(reqs) and reqs[nxt].arrival * time_scale <= t:
-            waiting.append(reqs[nxt])
+            r = reqs[nxt]
             nxt += 1
+            if results[r.rid].footprint > budget:
+                # It would never fit: reject at arrival, keep serving.
+                reject(r, _hd.HD_ERR_OOM, "needs %d bytes, more than the budget %d"
+                       % (results[r.rid].footprint, budget))
+                continue
+            waiting.append(r)
         # Admission in arrival order while the footprint fits.
         cap = None if batched else 1
         while waiting and (cap is None or len(running) < cap):
@@ -138,8 +156,12 @@ def serve(requests, precision="fp32", budget=None, batched=True, keep_states=Fal
             if used + fp > budget:
                 break
             waiting.pop(0)
-            s = make_solver(r.case, precision, tuned=tuned)
-            dt = setup(s, r.case)
+            try:
+                s = make_solver(r.case, precision, tuned=tuned)
+                dt = setup(s, r.case)
+            except _hd.HDError as e:
+                reject(r, e.status, str(e))
+                continue
             used += fp
             peak = max(peak, used)
             results[r.rid].admitted = now()
@@ -195,6 +217,7 @@ def serve(requests, precision="fp32", budget=None, batched=True, keep_states=Fal
             tc = now()
             for x in done:
                 x.res.completed = tc
+                x.res.status = "done"
                 x.res.mass, x.res.energy = x.solver.diagnostics()
                 if keep_states:
                     x.res.state = x.solver.get_state()
@@ -210,12 +233,14 @@ def serve(requests, precision="fp32", budget=None, batched=True, keep_states=Fal
         batch.close()
     makespan = now()
     res = [results[r.rid] for r in reqs]
-    lat = np.array([r.latency for r in res])
-    svc = np.array([r.service for r in res])
-    work = float(sum(r.ndofs * r.steps * 5 for r in res))
+    ok = [r for r in res if r.status == "done"]
+    lat = np.array([r.latency for r in ok]) if ok else np.array([np.nan])
+    svc = np.array([r.service for r in ok]) if ok else np.array([np.nan])
+    work = float(sum(r.ndofs * r.steps * 5 for r in ok))
     stats = {
-        "requests": len(res), "makespan_s": makespan,
-        "throughput_req_s": len(res) / makespan,
+        "requests": len(res), "completed": len(ok), "rejected": len(res) - len(ok),
+        "makespan_s": makespan,
+        "throughput_req_s": len(ok) / makespan,
         "dof_updates_per_s": work / makespan,
         "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
         "service_p50_s": float(np.percentile(svc, 50)), "service_p99_s": float(np.percentile(svc, 99)),

@@ -32,7 +32,8 @@ def make_mesh(dim_x, dim_v, cells, lo, hi) -> hd_mesh:
 
 
 class Solver:
-    """hd_create + hd_bind over a torch-allocated workspace on `device`."""
+    """hd_create + hd_bind over torch-allocated state and workspace buffers
+    on `device`."""
 
     def __init__(self, dim_x, dim_v, cells, lo, hi, degree, precision="fp64",
                  device="cuda:0", bind=True):
@@ -43,7 +44,7 @@ class Solver:
         self.lo = [float(x) for x in lo[: self.d]]
         self.hi = [float(x) for x in hi[: self.d]]
         self.precision = precision
-        self.prec = _hd.HD_FP32 if precision == "fp32" else _hd.HD_FP64
+        self.prec = _hd.HD_FP32_OP_FP64_ACC if precision == "fp32" else _hd.HD_FP64
         self.device = torch.device(device)
         self.mesh = make_mesh(dim_x, dim_v, cells, lo, hi)
         h = ctypes.c_void_p()
@@ -52,23 +53,36 @@ class Solver:
         n = ctypes.c_int64()
         check(self.lib.hd_num_dofs(self.h, ctypes.byref(n)))
         self.ndofs = n.value
-        b = ctypes.c_size_t()
-        check(self.lib.hd_required_bytes(self.h, ctypes.byref(b)))
-        self.workspace_bytes = b.value
+        sb = ctypes.c_size_t()
+        wb = ctypes.c_size_t()
+        check(self.lib.hd_required_bytes(self.h, ctypes.byref(sb), ctypes.byref(wb)))
+        self.state_bytes = sb.value
+        self.workspace_bytes = wb.value
+        self.state = None
         self.workspace = None
         if bind:
             self.bind()
 
+    @property
+    def device_bytes(self) -> int:
+        """Device memory of a bound solver: state and workspace buffers
+        (with their alignment slack)."""
+        return self.state_bytes + self.workspace_bytes + 2 * _ALIGN
+
     # -- memory -----------------------------------------------------------
-    def bind(self, workspace: torch.Tensor | None = None):
-        if workspace is None:
-            workspace = torch.empty(self.workspace_bytes + _ALIGN, dtype=torch.uint8,
-                                    device=self.device)
-        off = (-workspace.data_ptr()) % _ALIGN
-        self._ws_raw = workspace
-        self.workspace = workspace[off: off + self.workspace_bytes]
-        check(self.lib.hd_bind(self.h, ctypes.c_void_p(self.workspace.data_ptr()),
-                               self.workspace_bytes))
+    def bind(self, state: torch.Tensor | None = None, workspace: torch.Tensor | None = None):
+        """hd_bind over two torch uint8 device buffers (allocated here if not
+        given): the state (two FP64 solution vectors) and the workspace."""
+        def aligned(buf, nbytes):
+            if buf is None:
+                buf = torch.empty(nbytes + _ALIGN, dtype=torch.uint8, device=self.device)
+            off = (-buf.data_ptr()) % _ALIGN
+            assert buf.numel() - off >= nbytes, "buffer too small"
+            return buf, buf[off: off + nbytes]
+        self._st_raw, self.state = aligned(state, self.state_bytes)
+        self._ws_raw, self.workspace = aligned(workspace, self.workspace_bytes)
+        check(self.lib.hd_bind(self.h, ctypes.c_void_p(self.state.data_ptr()), self.state_bytes,
+                               ctypes.c_void_p(self.workspace.data_ptr()), self.workspace_bytes))
 
     def state_ptr(self) -> int:
         p = ctypes.c_void_p()
@@ -76,9 +90,9 @@ class Solver:
         return p.value
 
     def state_tensor(self) -> torch.Tensor:
-        """A float64 view of the current solution inside the workspace."""
-        off = self.state_ptr() - self.workspace.data_ptr()
-        return self.workspace[off: off + 8 * self.ndofs].view(torch.float64)
+        """A float64 view of the current solution inside the state buffer."""
+        off = self.state_ptr() - self.state.data_ptr()
+        return self.state[off: off + 8 * self.ndofs].view(torch.float64)
 
     # -- field ------------------------------------------------------------
     def set_field_constant(self, a):
@@ -155,7 +169,7 @@ class Solver:
     def apply(self, inp: torch.Tensor, out: torch.Tensor | None = None, stream=None):
         assert inp.dtype == torch.float64 and inp.is_cuda and inp.is_contiguous()
         assert inp.numel() == self.ndofs
-        odt = torch.float32 if self.prec == _hd.HD_FP32 else torch.float64
+        odt = torch.float32 if self.prec == _hd.HD_FP32_OP_FP64_ACC else torch.float64
         if out is None:
             out = torch.empty(self.ndofs, dtype=odt, device=inp.device)
         assert out.dtype == odt and out.is_contiguous() and out.numel() == self.ndofs
@@ -254,7 +268,9 @@ class Solver:
         if getattr(self, "h", None) is not None and self.h.value:
             self.lib.hd_destroy(self.h)
             self.h = ctypes.c_void_p()
+        self.state = None
         self.workspace = None
+        self._st_raw = None
         self._ws_raw = None
 
     def __del__(self):

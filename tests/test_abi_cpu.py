@@ -70,15 +70,19 @@ def test_lo_ge_hi_rejected_and_sizes():
     m = _mesh(3, 3, [8] * 6)
     assert lib.hd_create(ctypes.byref(m), 3, 0, ctypes.byref(h)) == 0
     n = ctypes.c_int64()
+    sb = ctypes.c_size_t()
     b = ctypes.c_size_t()
     assert lib.hd_num_dofs(h, ctypes.byref(n)) == 0 and n.value == 8 ** 6 * 4 ** 6
-    assert lib.hd_required_bytes(h, ctypes.byref(b)) == 0
-    # two FP64 solution buffers + FP64 du (3 vectors, Sec. 5.4) + small tables
-    # and the Vlasov-Poisson scratch (density partial sums over <= 2^20
-    # threads, transform buffers for 33^3 modes, and for the 6D degree-3
-    # kernel one velocity moment per 16 DoFs)
+    assert lib.hd_required_bytes(h, ctypes.byref(sb), ctypes.byref(b)) == 0
+    # state: two FP64 solution buffers; workspace: FP64 du (the third vector
+    # of Sec. 5.4) + small tables and the Vlasov-Poisson scratch (density
+    # partial sums over <= 2^20 threads, transform buffers for 33^3 modes,
+    # and for the 6D degree-3 kernel one velocity moment per 16 DoFs)
+    assert sb.value == 2 * 8 * n.value
     mom = 8 * (n.value // 16)
-    assert 3 * 8 * n.value + mom <= b.value < 3 * 8 * n.value + mom + (1 << 24)
+    assert 8 * n.value + mom <= b.value < 8 * n.value + mom + (1 << 24)
+    # a missing output pointer is rejected
+    assert lib.hd_required_bytes(h, ctypes.byref(sb), None) == -1
     # calls that need bound memory fail cleanly before hd_bind
     dt = ctypes.c_double()
     assert lib.hd_rk_step(h, ctypes.c_double(1e-3), 1, None) == -1
@@ -86,8 +90,9 @@ def test_lo_ge_hi_rejected_and_sizes():
     lib.hd_destroy(h)
     m = _mesh(3, 3, [8] * 6)
     assert lib.hd_create(ctypes.byref(m), 3, 1, ctypes.byref(h)) == 0
-    assert lib.hd_required_bytes(h, ctypes.byref(b)) == 0
-    assert 20 * n.value + mom <= b.value < 20 * n.value + mom + (1 << 24)  # FP32 du
+    assert lib.hd_required_bytes(h, ctypes.byref(sb), ctypes.byref(b)) == 0
+    assert sb.value == 2 * 8 * n.value
+    assert 4 * n.value + mom <= b.value < 4 * n.value + mom + (1 << 24)  # FP32 du
     lib.hd_destroy(h)
 
 
@@ -137,3 +142,56 @@ def test_autotune_cache_lookup(tmp_path):
     assert autotune.lookup(4, 3, "fp32", path=str(path), arch="gfx950") == plan
     assert autotune.lookup(4, 3, "fp64", path=str(path), arch="gfx950") is None
     assert autotune.lookup(4, 3, "fp32", path=str(tmp_path / "none.json"), arch="gfx950") is None
+
+
+def declared_signatures():
+    """name -> parameter list (text) of every function include/hd.h declares."""
+    text = open(os.path.join(ROOT, "include", "hd.h")).read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(hd_[a-z_0-9]+)\s*\(([^)]*)\)\s*;", text):
+        params = [p.strip() for p in m.group(2).split(",") if p.strip() and p.strip() != "void"]
+        out[m.group(1)] = params
+    return out
+
+
+def test_binding_argument_counts_match_the_header():
+    # The ctypes declarations marshal exactly the header's parameters.
+    lib = _lib()
+    sigs = declared_signatures()
+    assert set(sigs) == set(declared_symbols())
+    for name, params in sigs.items():
+        assert len(getattr(lib, name).argtypes) == len(params), (name, params)
+
+
+def test_boundary_signatures():
+    # State and workspace are separate caller-owned buffers; the FP32 mode is
+    # named for what it computes (FP32 operator, FP64 accumulation).
+    sigs = declared_signatures()
+    assert sigs["hd_required_bytes"] == ["const hd_solver *s", "size_t *state_bytes",
+                                         "size_t *workspace_bytes"]
+    assert sigs["hd_bind"] == ["hd_solver *s", "void *state_dev", "size_t state_bytes",
+                               "void *workspace_dev", "size_t workspace_bytes"]
+    text = open(os.path.join(ROOT, "include", "hd.h")).read()
+    assert re.search(r"HD_FP64\s*=\s*0\s*,\s*HD_FP32_OP_FP64_ACC\s*=\s*1", text)
+    from paper_2002_08110_amd import _hd
+    assert _hd.HD_FP64 == 0 and _hd.HD_FP32_OP_FP64_ACC == 1
+
+
+def test_bind_rejects_bad_buffers_without_gpu():
+    # Argument checks of hd_bind run before any device call.
+    lib = _lib()
+    m = _mesh(1, 1, [2, 2])
+    h = ctypes.c_void_p()
+    assert lib.hd_create(ctypes.byref(m), 2, 0, ctypes.byref(h)) == 0
+    sb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.hd_required_bytes(h, ctypes.byref(sb), ctypes.byref(wb)) == 0
+    base = 1 << 40  # never dereferenced: every case fails its checks first
+    S, W = ctypes.c_void_p(base), ctypes.c_void_p(base + (1 << 30))
+    assert lib.hd_bind(h, None, sb.value, W, wb.value) == -1
+    assert lib.hd_bind(h, S, sb.value - 8, W, wb.value) == -1
+    assert lib.hd_bind(h, S, sb.value, W, wb.value - 8) == -1
+    assert lib.hd_bind(h, ctypes.c_void_p(base + 8), sb.value, W, wb.value) == -1
+    assert lib.hd_bind(h, S, sb.value, ctypes.c_void_p(base + 256), wb.value) == -1  # overlap
+    assert b"overlap" in lib.hd_last_error()
+    lib.hd_destroy(h)

@@ -73,3 +73,27 @@ def test_one_at_a_time_baseline_matches_batched():
     for x, y in zip(sorted(a, key=lambda r: r.rid), sorted(b, key=lambda r: r.rid)):
         assert np.array_equal(x.state, y.state)
         assert x.mass == y.mass and x.energy == y.energy
+
+
+def test_over_budget_request_is_rejected_and_the_rest_are_served():
+    # A budget below the largest request's footprint: that request is
+    # rejected with a status (HD_ERR_OOM) when it arrives, and every other
+    # request is served and equals the same request alone, bitwise.
+    from paper_2002_08110_amd import _hd, serve
+    reqs = small_trace(seed=11, count=6)
+    fps = {q.rid: serve.footprint(q.case, "fp32") for q in reqs}
+    big = max(fps, key=fps.get)
+    budget = max(v for k, v in fps.items() if k != big)
+    assert fps[big] > budget
+    res, stats = serve.serve(reqs, precision="fp32", budget=budget, keep_states=True)
+    by_id = {r.rid: r for r in res}
+    assert by_id[big].status == "rejected" and by_id[big].code == _hd.HD_ERR_OOM
+    assert by_id[big].state is None
+    assert stats["rejected"] == 1 and stats["completed"] == len(reqs) - 1
+    assert stats["peak_bytes"] <= budget
+    for q in reqs:
+        if q.rid == big:
+            continue
+        assert by_id[q.rid].status == "done"
+        ref, _ = alone(q.case, "fp32")
+        assert np.array_equal(by_id[q.rid].state, ref), q.rid
