@@ -39,7 +39,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the serving trace in the default run")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0,
+                    help="seconds of the headline-mesh cell sample (CPU baseline extra)")
     ap.add_argument("--precisions", default="fp64,fp32")
     ap.add_argument("--plan", default="", help="override plan, e.g. lds=1,reg_dims=1")
     ap.add_argument("--no-tune", action="store_true",
@@ -478,31 +479,91 @@ def profiled_kernel(precision, plan_override, plan):
     return out
 
 
-def cpu_baseline(case, seconds):
-    """The oracle (zero-skipping mode, OpenMP over cells) on a bounded sample
-    of cells of the same workload; throughput in DoF updates per second."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_problem(case):
     import oracle
-    P = oracle.Problem(case.dim_x, case.dim_v, case.cells, case.lo, case.hi, case.degree,
-                       field="phase" if case.field == "sine" else "constant",
-                       sine_amp=case.amp if case.field == "sine" else None, a=case.a)
+    if case.field == "sine":
+        return oracle.Problem(case.dim_x, case.dim_v, case.cells, case.lo, case.hi, case.degree,
+                              field="phase", sine_amp=case.amp)
+    return oracle.Problem(case.dim_x, case.dim_v, case.cells, case.lo, case.hi, case.degree,
+                          field="constant", a=case.a)
+
+
+def oracle_configs(precisions, sample_seconds):
+    """The oracle (zero-skipping mode, FP64, OpenMP over cells on the host
+    cores) run over each configuration that it finishes in about a minute:
+    the 2D configuration (100 steps), the 4D configuration (16^4 cells, 20
+    steps) and the 4^6-cell rerun of the 6D configuration (10 steps). Every
+    stage (operator plus LSRK update) is timed; the CPU baseline is the
+    median over the stages after the first (the warm-up). The final states
+    are the references of the GPU runs of the same configurations, in each
+    precision: the FP32 operator mode's error per configuration. A sample of
+    the 8^6 headline mesh's cells (operator only) is timed as an extra."""
+    import oracle
+    import torch
+    from paper_2002_08110_amd import workloads as W
+    out = {"cores": oracle.num_threads(), "cpu_model": cpu_model(), "configs": {}}
+    for case in (W.CONFIG_2D, W.CONFIG_4D, W.CONFIG_6D_SMALL):
+        P = _oracle_problem(case)
+        u = P.init_state(case.ic, list(case.ic_params))
+        du = np.zeros_like(u)
+        L = np.empty_like(u)
+        dt = P.stable_dt(case.cfl)
+        times = []
+        w0 = time.perf_counter()
+        for _ in range(case.steps):
+            for st in range(5):
+                t = time.perf_counter()
+                P.rk_stage(u, du, L, dt, st)
+                times.append(time.perf_counter() - t)
+        med = float(np.median(times[1:]))
+        rec = {"ndofs": P.ndofs, "steps": case.steps, "stages_timed": len(times) - 1,
+               "oracle_stage_s_median": med, "oracle_dof_updates_per_s": P.ndofs / med,
+               "oracle_run_s": time.perf_counter() - w0}
+        e_ref = P.diagnostics(u)[1]
+        for prec in precisions:
+            S = _make_solver(case, prec)
+            S.rk_step(dt, case.steps)
+            got = S.get_state()
+            S.close()
+            rec[prec + "_rel_l2"] = float(np.linalg.norm(got - u) / np.linalg.norm(u))
+            rec[prec + "_rel_l2_weighted"] = float(np.sqrt(P.diagnostics(got - u)[1] / e_ref))
+        torch.cuda.empty_cache()
+        out["configs"][case.name] = rec
+        print("# oracle %s: %.3f s per stage (%.3e DoF-updates/s); GPU vs oracle %s"
+              % (case.name, med, P.ndofs / med,
+                 ", ".join("%s %.2e" % (p, rec[p + "_rel_l2"]) for p in precisions)),
+              file=sys.stderr, flush=True)
+        del u, du, L
+    # Extra: a bounded random sample of the headline mesh's cells.
+    case = W.CONFIG_6D
+    P = _oracle_problem(case)
     nd = P.n ** P.d
     u = np.zeros(P.ndofs)  # pages the sample never touches stay unallocated
     rng = np.random.default_rng(5)
-    ncells = P.ncells
-    # Calibrate on a few cells, then size the sample to about `seconds`.
-    sample = rng.choice(ncells, size=min(ncells, 64), replace=False).astype(np.int64)
+    sample = rng.choice(P.ncells, size=min(P.ncells, 64), replace=False).astype(np.int64)
     t = time.perf_counter()
     P.apply_cells(u, sample)
     per_cell = (time.perf_counter() - t) / len(sample)
-    count = int(min(ncells, max(64, seconds / max(per_cell, 1e-9))))
-    sample = rng.choice(ncells, size=count, replace=False).astype(np.int64)
+    count = int(min(P.ncells, max(64, sample_seconds / max(per_cell, 1e-9))))
+    sample = rng.choice(P.ncells, size=count, replace=False).astype(np.int64)
     t = time.perf_counter()
     P.apply_cells(u, sample)
     el = time.perf_counter() - t
-    return {"value": count * nd / el, "unit": "DoF-updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": "%d of %d cells of %s (operator evaluation per cell, zero-skipping mode), "
-                      "%.1f s" % (count, ncells, case.name, el)}
+    out["headline_cell_sample"] = {
+        "value": count * nd / el, "unit": "DoF/s (operator only)",
+        "sample": "%d of %d cells of %s, %.1f s" % (count, P.ncells, case.name, el)}
+    return out
 
 
 def main():
@@ -606,8 +667,22 @@ def main():
         print("# serving: p50 %.3f s, p99 %.3f s (one at a time FP64: %.3f / %.3f s)"
               % (b["latency_p50_s"], b["latency_p99_s"], f["latency_p50_s"], f["latency_p99_s"]),
               file=sys.stderr, flush=True)
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
+    if not args.no_cpu_baseline and args.config == "6d":
+        orc = oracle_configs(list(results), args.cpu_seconds)
+        six = orc["configs"][W.CONFIG_6D_SMALL.name]
+        line["cpu_baseline"] = {
+            "value": six["oracle_dof_updates_per_s"], "unit": "DoF-updates/s",
+            "cores": orc["cores"], "cpu_model": orc["cpu_model"], "kind": "oracle",
+            "sample": "the 6D k=3 phase-space workload at 4^6 cells (its reduced rerun, %d DoFs): "
+                      "median of %d full LSRK stages (operator + update) after one warm-up stage"
+                      % (six["ndofs"], six["stages_timed"]),
+            "per_config": {name: {k: r[k] for k in ("ndofs", "oracle_stage_s_median",
+                                                    "oracle_dof_updates_per_s", "stages_timed")}
+                           for name, r in orc["configs"].items()},
+            "headline_cell_sample": orc["headline_cell_sample"]}
+        line["fp32_error_vs_fp64_oracle"] = {
+            name: {k: r[k] for k in r if k.endswith("rel_l2") or k.endswith("rel_l2_weighted")}
+            | {"steps": r["steps"]} for name, r in orc["configs"].items()}
     print(json.dumps(line), flush=True)
 
 

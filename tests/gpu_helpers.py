@@ -116,3 +116,39 @@ def all_plans(case: W.Case, precision="fp64"):
 def k3_eligible(case: W.Case):
     """The specialised kernel: 6D (3 x + 3 v), degree 3, < 2^31 DoFs."""
     return case.dim_x == 3 and case.dim_v == 3 and case.degree == 3 and case.ndofs < 2 ** 31
+
+
+def sample_cells(ncells, seed, count=24):
+    """The corners of the periodic box (wrap-around neighbours), the middle
+    cell and a seeded random sample."""
+    rng = np.random.default_rng(seed)
+    fixed = [0, ncells - 1, ncells // 2]
+    return np.unique(np.concatenate([fixed, rng.integers(0, ncells, count)])).astype(np.int64)
+
+
+def stages_sampled(S, problem_of, cells, dt, tol, mode=1):
+    """One RK step of the GPU solver S, stage by stage as its launches run
+    them, checked on the sampled cells: the increment is local to a cell, so
+    before each stage the oracle problem of the current state
+    (problem_of(host_state)) evaluates L on the samples from the full device
+    state, and du and u are followed there (Sec. 5.4 update). Returns the
+    largest relative L2 error over the stages."""
+    import torch
+    A, B, _ = oracle.lsrk45_coefficients()
+    nd = (S.k + 1) ** S.d
+    idx = (cells[:, None] * nd + np.arange(nd)[None, :]).reshape(-1)
+    idx_t = torch.from_numpy(idx).to(S.device)
+    host = np.empty(S.ndofs)
+    du = np.zeros(len(idx))
+    worst = 0.0
+    for st in range(5):
+        host[:] = S.state_tensor().cpu().numpy()
+        us = host[idx]
+        L = problem_of(host).apply_cells(host, cells, mode=mode)
+        du = A[st] * du + dt * L
+        S.rk_stage(st, dt)
+        got = S.state_tensor()[idx_t].cpu().numpy()
+        err = rel_l2(got - us, B[st] * du)
+        assert err <= tol, (st, err)
+        worst = max(worst, err)
+    return worst

@@ -6,7 +6,8 @@ from the same input and the outputs are compared cell by cell.
 import numpy as np
 import pytest
 
-from gpu_helpers import TOL_FP64, gpu_solver, oracle_problem, rel_l2, rel_max
+from gpu_helpers import (TOL_FP64, gpu_solver, oracle_problem, rel_l2, rel_max, sample_cells,
+                         stages_sampled)
 from paper_2002_08110_amd import workloads as W
 
 torch = pytest.importorskip("torch")
@@ -110,4 +111,80 @@ def test_headline_gauss_legendre_operator_sampled(precision):
     assert rel_l2(got, ref) <= tol
     if precision == "fp64":
         assert rel_max(got, ref) <= tol
+    S.close()
+
+
+def _random_state_on(S, seed):
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    u = torch.randn(S.ndofs, dtype=torch.float64, device="cuda", generator=g)
+    S.set_state(u)
+    return u
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("quadrature", ["gauss_lobatto", "gauss_legendre"])
+def test_headline_mapped_cells_sampled(quadrature, precision):
+    # The 6D degree-3 kernels on deformed configuration cells at the
+    # headline size, in the benchmark's launch configuration (collocation:
+    # stage_k3m_kernel, always one slab per XCD; Gauss-Legendre:
+    # stage_k3mg_kernel): the operator on sampled cells against the
+    # oracle's mapped weak form (mode 0 collocation, mode 2 Gauss), and in
+    # FP64 one whole step stage by stage.
+    import oracle
+    case = W.CONFIG_6D
+    eps = 0.02
+    mode = 0 if quadrature == "gauss_lobatto" else 2
+    S = gpu_solver(case, precision)
+    if quadrature == "gauss_legendre":
+        S.set_quadrature(quadrature)
+    S.set_mapping(eps)
+    S.set_field_sine(case.amp)
+    assert S.get_plan()["kernel"] == 1
+    P = oracle.Problem(case.dim_x, case.dim_v, case.cells, case.lo, case.hi, case.degree,
+                       field="phase", sine_amp=case.amp, map_eps=eps)
+    u = _random_state_on(S, 4242 + mode)
+    nd = (case.degree + 1) ** case.d
+    cells = sample_cells(S.ndofs // nd, seed=37 + mode, count=5)
+    out = S.apply(u)
+    ref = P.apply_cells(u.cpu().numpy(), cells, mode=mode).reshape(len(cells), nd)
+    idx = (cells[:, None] * nd + np.arange(nd)[None, :]).reshape(-1)
+    got = out[torch.from_numpy(idx).cuda()].double().cpu().numpy().reshape(len(cells), nd)
+    del out, u
+    tol = TOL_FP64 if precision == "fp64" else 5e-6
+    assert rel_l2(got, ref) <= tol
+    if precision == "fp64":
+        assert rel_max(got, ref) <= tol
+        dt = S.stable_dt(case.cfl)
+        stages_sampled(S, lambda host: P, cells[:4], dt, TOL_FP64, mode=mode)
+    S.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_headline_vlasov_poisson_stages_sampled(precision):
+    # The self-consistent field at the headline size: the first stage of a
+    # step takes the density from the state, the later ones from the
+    # velocity moments the previous stage kernel wrote with its output. After
+    # each stage the oracle computes the density and field of the full
+    # device state (Sec. 6 steps 1-3) and the operator on sampled cells.
+    import oracle
+    case = W.landau_case("landau_6d_8^6_k3", 3, [8] * 6, 3, 1, modes=4)
+    S = gpu_solver(case, precision)
+    assert S.get_plan()["kernel"] == 1
+    S.init_state(case.ic, list(case.ic_params))
+    # a seeded perturbation on top of the Landau state (density of full
+    # entropy in every velocity cell)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(808)
+    st = S.state_tensor()
+    st += 1e-3 * torch.randn(S.ndofs, dtype=torch.float64, device="cuda", generator=g)
+    del st
+    vp = oracle.VlasovPoisson(case.dim_x, case.dim_v, case.cells, case.lo, case.hi, case.degree,
+                              case.modes)
+    nd = (case.degree + 1) ** case.d
+    cells = sample_cells(S.ndofs // nd, seed=55, count=10)
+    dt = S.stable_dt(case.cfl)
+    tol = TOL_FP64 if precision == "fp64" else 5e-6
+    worst = stages_sampled(S, vp.advection, cells, dt, tol)
+    print("vlasov-poisson 8^6 stages: worst rel-L2 %.3e (%s)" % (worst, precision))
     S.close()

@@ -259,3 +259,37 @@ def test_6d_k3_gauss_legendre_rk_steps_on_mapped_cells(precision):
     S.rk_step(dt, case.steps)
     assert rel_l2(S.get_state(), ref) <= (TOL_FP64 if precision == "fp64" else 1e-5)
     S.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("quadrature,field", [("gauss_lobatto", "sine"), ("gauss_lobatto", "table"),
+                                              ("gauss_legendre", "sine"),
+                                              ("gauss_legendre", "table")])
+def test_6d_k3_mapped_kernels_with_distinct_neighbours(quadrature, field, precision):
+    # Three cells in every dimension: each cell's left and right neighbours
+    # are distinct cells, different from itself, so the upwind choice of the
+    # neighbour side and the cell order of the launch are exercised. The
+    # default kernels of mapped 6D degree 3 (collocation and Gauss-Legendre
+    # layouts) on sampled cells against the oracle, and in FP64 one RK step
+    # stage by stage.
+    from gpu_helpers import sample_cells, stages_sampled
+    case = case_of(6, 3, field)
+    case.cells = [3] * 6
+    E = W.random_field_table(x_table_size(case), seed=19) if field == "table" else None
+    P = oracle_of(case, E)
+    mode = 0 if quadrature == "gauss_lobatto" else 2
+    S = solver_of(case, precision, quadrature, E)
+    assert S.get_plan()["kernel"] == 1
+    u = W.random_state(P.ndofs, seed=61)
+    cells = sample_cells(P.ncells, seed=63, count=9)
+    ref = P.apply_cells(u, cells, mode=mode)
+    nd = 4 ** 6
+    idx = (cells[:, None] * nd + np.arange(nd)[None, :]).reshape(-1)
+    out = S.apply(torch.from_numpy(u).cuda()).double().cpu().numpy()[idx]
+    tol = TOL_FP64 if precision == "fp64" else 5e-6
+    assert rel_l2(out, ref) <= tol
+    if precision == "fp64":
+        assert rel_max(out, ref) <= TOL_FP64
+        S.set_state(u)
+        stages_sampled(S, lambda host: P, cells[:6], S.stable_dt(0.2), TOL_FP64, mode=mode)
+    S.close()
