@@ -315,6 +315,24 @@ hd_status hd_rk_step(hd_solver *s, double dt, int nsteps, hd_stream stream);
  * Synchronizes `stream`. Requires hd_bind. */
 hd_status hd_diagnostics(const hd_solver *s, double *mass, double *energy, hd_stream stream);
 
+/* hd_diagnostics for callers that cannot allocate memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same two reduction kernels, in the same fixed order (bitwise equal to
+ * hd_diagnostics on the same vector), with the partial sums in a
+ * file-scope device array of the library instead of the workspace.
+ *   s        a created solver (it need not be bound): mesh, degree, mapping;
+ *   u_dev    FP64 device vector of hd_num_dofs values, canonical layout;
+ *   res_dev  device memory for 2 doubles: res_dev[0] = mass,
+ *            res_dev[1] = energy (written by a kernel on `stream`).
+ * Enqueues two kernels on `stream` and returns; calls no allocating
+ * routine and does not synchronize. The array holds 1024 partial pairs
+ * (16 KiB per GPU, kept until the process ends); every call on one GPU
+ * shares it, so calls that overlap on one GPU (other streams, other
+ * threads) race and must be ordered by the caller. Limit: at most 2^40
+ * DoFs, else HD_ERR_INVALID; NULL arguments give HD_ERR_INVALID. */
+hd_status hd_diagnostics_noalloc(const hd_solver *s, const double *u_dev, double *res_dev,
+                                 hd_stream stream);
+
 /* Read / override the stage-kernel launch plan (hd_plan above). Plans
  * change how the kernels map cells and nodes onto the GPU, never the
  * result beyond rounding order; they have no counterpart in the paper,

@@ -56,6 +56,9 @@ using hd::rt::kRkB;
 constexpr size_t kAlign = 256;
 constexpr int kDiagBlocks = 1024;
 constexpr int kDiagThreads = 256;
+// Largest mesh of the allocation-free diagnostics: 2^40 DoFs, so that a block's
+// chunk (ndofs / 1024) stays within 2^30 values.
+constexpr long long kNoAllocMaxDofs = 1LL << 40;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -1244,6 +1247,66 @@ hd_status hd_diagnostics(const hd_solver *s, double *mass, double *energy, hd_st
   HD_HIP(hipStreamSynchronize(st));
   *mass = res[0];
   *energy = res[1];
+  return HD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Partial sums of the allocation-free diagnostics (hd_diagnostics_noalloc):
+// one (mass, energy) pair per block of the first reduction pass. Each GPU
+// holds its own copy of this array until the process ends; host code uses
+// the device address taken with hipGetSymbolAddress, never the name.
+constexpr int kScratchPairs = kDiagBlocks;
+static __device__ __align__(256) double scratch[2 * kScratchPairs];
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// The device address of `scratch` on the current device, taken once per
+// device (with that device current) and kept.
+hd_status scratch_ptr(double **out) {
+  int dev = -1;
+  HD_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxScratchDevices)
+    return fail(HD_ERR_UNSUPPORTED, "device ordinal beyond the scratch table (64 devices)");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HD_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(HD_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[dev] = static_cast<double *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return HD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hd_status hd_diagnostics_noalloc(const hd_solver *s, const double *u_dev, double *res_dev,
+                                 hd_stream stream) {
+  if (!s || !u_dev || !res_dev) return fail(HD_ERR_INVALID, "NULL argument");
+  // The first pass writes one pair per block; the array holds kScratchPairs.
+  static_assert(kDiagBlocks <= kScratchPairs, "scratch holds every partial pair");
+  if (s->ndofs > kNoAllocMaxDofs)
+    return fail(HD_ERR_INVALID, "hd_diagnostics_noalloc: more than 2^40 DoFs (the limit of its "
+                                "fixed 1024-block reduction)");
+  double *part = nullptr;
+  hd_status r = scratch_ptr(&part);
+  if (r) return r;
+  const GeomArgs g = geom_of(s);
+  const long long chunk = (s->ndofs + kDiagBlocks - 1) / kDiagBlocks;
+  hipStream_t st = (hipStream_t)stream;
+  // Every pair is written by its block (empty chunks write zeros), so
+  // nothing needs clearing between calls.
+  hipLaunchKernelGGL(diag_kernel1, dim3(kDiagBlocks), dim3(kDiagThreads), 0, st, g, u_dev, chunk,
+                     part);
+  HD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(diag_kernel2, dim3(1), dim3(kDiagThreads), 0, st, part, kDiagBlocks, res_dev);
+  HD_HIP(hipGetLastError());
   return HD_OK;
 }
 

@@ -195,3 +195,20 @@ def test_bind_rejects_bad_buffers_without_gpu():
     assert lib.hd_bind(h, S, sb.value, ctypes.c_void_p(base + 256), wb.value) == -1  # overlap
     assert b"overlap" in lib.hd_last_error()
     lib.hd_destroy(h)
+
+
+def test_noalloc_diagnostics_rejects_null_and_oversized_meshes_before_any_device_call():
+    # Both checks return before the entry point touches a device.
+    lib = _lib()
+    h = ctypes.c_void_p()
+    m = _mesh(3, 3, [32, 32, 32, 32, 32, 1])
+    assert lib.hd_create(ctypes.byref(m), 5, 0, ctypes.byref(h)) == 0
+    n = ctypes.c_int64()
+    assert lib.hd_num_dofs(h, ctypes.byref(n)) == 0 and n.value > 2 ** 40
+    fake = ctypes.c_void_p(256)
+    assert lib.hd_diagnostics_noalloc(h, fake, fake, None) == -1
+    assert b"2^40" in lib.hd_last_error()
+    assert lib.hd_diagnostics_noalloc(h, None, fake, None) == -1
+    assert lib.hd_diagnostics_noalloc(h, fake, None, None) == -1
+    assert lib.hd_diagnostics_noalloc(None, fake, fake, None) == -1
+    lib.hd_destroy(h)
