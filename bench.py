@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="6d", choices=["6d", "4d", "6d_small", "2d"])
+    ap.add_argument("--config", default="6d", choices=["6d", "4d", "6d_small", "2d", "6d_k4", "6d_k5"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the serving trace in the default run")
@@ -57,12 +57,15 @@ def parse():
                          "mapped: the workload on a deformed configuration mesh")
     ap.add_argument("--map-eps", type=float, default=0.02,
                     help="mapped: deformation amplitude of the configuration mesh")
+    ap.add_argument("--stages-map-eps", type=float, default=0.0,
+                    help="stages: deform the configuration mesh by this amplitude")
     ap.add_argument("--quadrature", default="gauss_lobatto",
                     choices=["gauss_lobatto", "gauss_legendre"],
                     help="stages: quadrature of the profiled run")
     ap.add_argument("--modes", type=int, default=4, help="vp: Fourier modes per x-dimension")
     ap.add_argument("--copy-mib", type=int, default=4096)
-    ap.add_argument("--requests", type=int, default=24, help="serve: trace prefix length")
+    ap.add_argument("--requests", type=int, default=24, help="serve: trace segment length")
+    ap.add_argument("--start", type=int, default=0, help="serve: first request of the segment")
     ap.add_argument("--steps-scale", type=float, default=1.0,
                     help="serve: factor on each request's step count")
     ap.add_argument("--fill-dofs", type=float, default=1e8,
@@ -72,13 +75,15 @@ def parse():
     return ap.parse_args()
 
 
-def run_stages(case, precision, steps, plan_override, quadrature="gauss_lobatto"):
+def run_stages(case, precision, steps, plan_override, quadrature="gauss_lobatto", map_eps=0.0):
     """Only the fused stage launches (5 per step), for counter collection."""
     import torch
 
     from paper_2002_08110_amd.solver import Solver
     S = Solver(case.dim_x, case.dim_v, case.cells, case.lo, case.hi, case.degree,
                precision=precision)
+    if map_eps:
+        S.set_mapping(map_eps)  # before the field: node coordinates follow the mapping
     if case.field == "sine":
         S.set_field_sine(case.amp)
     else:
@@ -219,10 +224,11 @@ def _make_solver(case, precision, tuned=False):
 
 def run_batch(steps, seq_steps):
     """The seeded mix of 96 uneven solves (6D and lower, degrees 2-5) advanced
-    together: per RK stage one persistent launch per group of solves sharing
-    a launch plan (the autotuned plan of each (d, k)), one hipGraph per step,
-    FP32 operator mode. Compared with the same solves, same plans, stepped one
-    after another (FP32, then FP64). Prints one JSON line."""
+    together, FP32 operator mode, the autotuned plan of each (d, k): one
+    hipGraph replay per step, per RK stage one work-list launch per group of
+    solves sharing a kernel variant and launch shape. Compared with the same
+    solves, same plans, stepped one after another (FP32, then FP64). Prints
+    one JSON line."""
     import torch
 
     from paper_2002_08110_amd import workloads as W
@@ -246,9 +252,12 @@ def run_batch(steps, seq_steps):
     dts = [S.stable_dt(c.cfl) for S, c in zip(solvers, cases)]
     B = Batch(solvers)
     B.step(dts)
+    B.step(dts)  # both solution-buffer parities captured
     t = timed(lambda: [B.step(dts) for _ in range(steps)])
     res["value"] = total * 5 * steps / t
     res["batched_fp32_s"] = t
+    nlist, nown = B.launch_counts()
+    res["launches_per_step"] = {"work_list": nlist, "single_solve": nown}
     t_seq = timed(lambda: [S.rk_step(dt, seq_steps) for S, dt in zip(solvers, dts)])
     res["sequential_fp32"] = total * 5 * seq_steps / t_seq
     B.close()
@@ -267,8 +276,8 @@ def run_batch(steps, seq_steps):
     print(json.dumps(res), flush=True)
 
 
-def run_serve(n_requests, steps_scale, load, fill, quiet=False):
-    """The first n_requests requests of the seeded serving trace (Poisson
+def run_serve(n_requests, steps_scale, load, fill, quiet=False, start=0):
+    """n_requests consecutive requests (from index `start`) of the seeded serving trace (Poisson
     arrivals at 20 req/s; d in {4,5,6}, k in {2..5}, 1e6-2e9 DoFs), each
     request's step count scaled by steps_scale, served with continuous
     batching in FP32 operator mode, and one at a time in FP64 on the same
@@ -277,7 +286,10 @@ def run_serve(n_requests, steps_scale, load, fill, quiet=False):
     Returns the results; prints them as one JSON line unless quiet."""
     from paper_2002_08110_amd import serve
     from paper_2002_08110_amd import workloads as W
-    trace = W.serve_trace()[:n_requests]
+    trace = W.serve_trace()[start:start + n_requests]
+    t_first = trace[0].arrival
+    for q in trace:
+        q.arrival -= t_first  # the segment starts at time 0
     for q in trace:
         q.case.steps = max(1, int(round(q.case.steps * steps_scale)))
     work = float(sum(q.case.ndofs * q.case.steps * 5 for q in trace))
@@ -288,7 +300,8 @@ def run_serve(n_requests, steps_scale, load, fill, quiet=False):
             print("# " + msg, file=sys.stderr, flush=True)
 
     out = {"metric": "served DoF-updates/s and completion latency (request trace)",
-           "requests": len(trace), "steps_scale": steps_scale, "work_dof_updates": work,
+           "requests": len(trace), "first_request": start, "steps_scale": steps_scale,
+           "work_dof_updates": work,
            "dofs_max": max(q.case.ndofs for q in trace),
            "dofs_mean": float(np.mean([q.case.ndofs for q in trace]))}
     _, b = serve.serve(trace, precision="fp32", batched=True, log=log, fill_dofs=fill)
@@ -579,7 +592,7 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
     case = {"6d": W.CONFIG_6D, "4d": W.CONFIG_4D, "6d_small": W.CONFIG_6D_SMALL,
-            "2d": W.CONFIG_2D}[args.config]
+            "2d": W.CONFIG_2D, "6d_k4": W.CONFIG_6D_K4, "6d_k5": W.CONFIG_6D_K5}[args.config]
     plan = {}
     if args.plan:
         for kv in args.plan.split(","):
@@ -592,7 +605,7 @@ def main():
         run_batch(args.steps, max(1, args.steps // 5))
         return
     if args.mode == "serve":
-        run_serve(args.requests, args.steps_scale, args.load, args.fill_dofs)
+        run_serve(args.requests, args.steps_scale, args.load, args.fill_dofs, start=args.start)
         return
     if args.mode == "vp":
         run_vp(args.steps, args.warmup, args.precisions.split(","), args.modes)
@@ -605,7 +618,7 @@ def main():
         return
     if args.mode == "stages":
         for prec in args.precisions.split(","):
-            run_stages(case, prec, args.steps, plan, args.quadrature)
+            run_stages(case, prec, args.steps, plan, args.quadrature, args.stages_map_eps)
         return
     results = {}
     for prec in args.precisions.split(","):
@@ -667,6 +680,21 @@ def main():
         print("# serving: p50 %.3f s, p99 %.3f s (one at a time FP64: %.3f / %.3f s)"
               % (b["latency_p50_s"], b["latency_p99_s"], f["latency_p50_s"], f["latency_p99_s"]),
               file=sys.stderr, flush=True)
+        # A later segment of the same trace holding three requests of 1.2e9-1.5e9
+        # DoFs (requests 24-47, step counts scaled by 1/4 to keep the run short).
+        sv = run_serve(24, 0.25, 0.0, args.fill_dofs, quiet=True, start=24)
+        b, f = sv["batched_fp32"], sv["one_at_a_time_fp64"]
+        line["serving_large"] = {
+            "requests": sv["requests"], "first_request": 24, "steps_scale": 0.25,
+            "dofs_max": sv["dofs_max"], "offered_load": sv["offered_load"],
+            "latency_p99_s": b["latency_p99_s"], "latency_p50_s": b["latency_p50_s"],
+            "dof_updates_per_s": b["dof_updates_per_s"], "throughput_req_s": b["throughput_req_s"],
+            "peak_bytes": b["peak_bytes"], "precision": "fp32 operator, batched",
+            "one_at_a_time_fp64": {k: f[k] for k in ("latency_p99_s", "latency_p50_s",
+                                                     "dof_updates_per_s", "throughput_req_s")}}
+        print("# serving (segment with 1.5e9-DoF requests): p50 %.3f s, p99 %.3f s (one at a time "
+              "FP64: %.3f / %.3f s)" % (b["latency_p50_s"], b["latency_p99_s"], f["latency_p50_s"],
+                                         f["latency_p99_s"]), file=sys.stderr, flush=True)
     if not args.no_cpu_baseline and args.config == "6d":
         orc = oracle_configs(list(results), args.cpu_seconds)
         six = orc["configs"][W.CONFIG_6D_SMALL.name]

@@ -356,13 +356,21 @@ const char *hd_last_error(void);
 /* Batched stepping of many independent solves (Sec. 5.4 time stepping of
  * each; any d, degree, size, precision and plan in one batch).
  * hd_batch_step advances every active solve by one LSRK step with ONE
- * hipGraph replay: each solve's five fused stage launches - the same
- * kernels and parameters as the solve stepped alone, so its result is
- * bitwise the same - form a chain, and the chains run on up to eight
- * independent graph branches. The graph is captured at the first step and
- * again whenever the active set, a time step, a solution-buffer parity or a
- * solver's plan, field or memory changed; two graphs are cached
- * (alternating parities).
+ * hipGraph replay. Per RK stage, the solves whose stage kernel has a
+ * work-list form (collocation on Cartesian cells with a prescribed field)
+ * are grouped by kernel variant and launch shape, and each group is ONE
+ * launch over a work list of (solve, tile) items, one workgroup per item,
+ * running the solve's own stage body with its own parameters; the others
+ * (Gauss-Legendre, mapped cells, the Vlasov-Poisson field, or a variant
+ * whose work-list form would hold fewer workgroups per CU or more scratch
+ * than its own launch) keep their own stage launches in the same graph.
+ * Either way a solve's result is bitwise the same alone and in the batch.
+ * The kernel parameters and work lists are built and checked on the host,
+ * uploaded into device memory of the batch before the graph is captured,
+ * and freed only after that graph's last replay. The graph is captured at
+ * the first step and again whenever the active set, a time step, a
+ * solution-buffer parity or a solver's plan, field or memory changed; two
+ * graphs are cached (alternating parities).
  * Ownership: `solvers` (n pointers, read during the call) stay owned by the
  * caller, must stay bound and outlive the batch; destroying or re-binding
  * a member while the batch is used is undefined.
@@ -381,6 +389,12 @@ hd_status hd_batch_destroy(hd_batch *b);
  * solve, or a member that lost its workspace; HD_ERR_HIP for capture or
  * launch failures. */
 hd_status hd_batch_step(hd_batch *b, const double *dt, const int *active, hd_stream stream);
+
+/* Launches in the most recently captured step of b: work-list launches (one
+ * per kernel-variant group and stage) and stage launches of single solves.
+ * Both 0 before the first step. (Bookkeeping of this interface.)
+ * Errors: HD_ERR_INVALID for NULL arguments. */
+hd_status hd_batch_launch_counts(const hd_batch *b, int *list_launches, int *solve_launches);
 
 #ifdef __cplusplus
 }

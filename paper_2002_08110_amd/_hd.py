@@ -28,7 +28,7 @@ SYMBOLS = (
     "hd_set_state", "hd_init_state", "hd_state_ptr", "hd_get_state", "hd_apply",
     "hd_stable_dt", "hd_rk_stage", "hd_rk_step", "hd_diagnostics", "hd_get_plan",
     "hd_set_plan", "hd_last_error", "hd_batch_create", "hd_batch_destroy",
-    "hd_batch_step", "hd_stream_copy", "hd_diagnostics_noalloc",
+    "hd_batch_step", "hd_stream_copy", "hd_diagnostics_noalloc", "hd_batch_launch_counts",
 )
 
 
@@ -103,6 +103,7 @@ def load():
         "hd_batch_step": ([vp, P(d), P(i), vp], st),
         "hd_stream_copy": ([vp, vp, ctypes.c_size_t, vp], st),
         "hd_diagnostics_noalloc": ([vp, vp, vp, vp], st),
+        "hd_batch_launch_counts": ([vp, P(i), P(i)], st),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

@@ -125,11 +125,33 @@ inline bool k3mg_used(const hd_solver *s) {
 // solver's plan.
 hd::LaunchShape shape_of(const hd_solver *s);
 
-// Entry of the compiled stage kernel of the solver's plan; nullptr if none
-// is compiled.
 // The stage kernel of the solver's plan; k3_role selects the 6D degree-3
-// kernel's variant (0 general, 1 first stage, 2 late increment).
-const void *stage_entry(const hd_solver *s, int k3_role = 0);
+// kernel's variant (0 general, 1 first stage, 2 late increment); list != 0
+// its work-list form (stage_list_kernel / stage_k3_list_kernel; only for
+// solves with list_capable), nullptr if none is compiled.
+const void *stage_entry(const hd_solver *s, int k3_role = 0, int list = 0);
+
+// The stages of s run the generic kernel or the 6D degree-3 collocation
+// kernel on Cartesian cells with a prescribed field: kernels with a
+// work-list form. (The Gauss-Legendre and mapped-cell kernels take a second
+// table argument, and the Vlasov-Poisson field adds per-solve launches.)
+inline bool list_capable(const hd_solver *s) {
+  return s->quad == 0 && !s->mapped() && s->field_kind != 2;
+}
+
+// Kernel parameters, launch shape and 6D degree-3 role of one operator
+// application (mode 0: out = L(in)) or fused RK stage (mode 1: in -> u_out,
+// increment in the workspace) of s: exactly what its own launch uses.
+template <typename P>
+void fill_stage(const hd_solver *s, const double *in, void *out, double *u_out, int mode, int stage,
+                double dt, StageParams<P> *prm, LaunchShape *ls, int *k3_role);
+
+// Enqueue stage `stage` of one RK step of s on st, from solution buffer par
+// to 1 - par (as enqueue_step does for each of its five stages).
+hd_status enqueue_stage_of(hd_solver *s, int par, int stage, double dt, hipStream_t st);
+
+// Let kernel fn use up to 160 KiB of LDS minus its static LDS (once per entry).
+hipError_t allow_large_lds(const void *fn);
 
 // Enqueue the five fused stages of one RK step of s on st, starting from
 // solution buffer `par` (the solution ends in buffer 1 - par). s->cur is

@@ -247,22 +247,23 @@ hd::LaunchShape hd::rt::shape_of(const hd_solver *s) {
 namespace hd {
 namespace rt {
 
-const void *stage_entry(const hd_solver *s, int k3_role) {
+const void *stage_entry(const hd_solver *s, int k3_role, int list) {
   const bool f32 = s->prec == HD_FP32_OP_FP64_ACC;
+  if (list && !list_capable(s)) return nullptr;
   if (k3g_used(s)) return hd::stage_k3g_entry(f32);
   if (k3m_used(s)) return hd::stage_k3m_entry(f32);
   if (k3mg_used(s)) return hd::stage_k3mg_entry(f32);
   if (s->quad == 1 || s->mapped()) return hd::stage_gauss_entry(s->d, s->n, f32, s->mapped());
-  if (s->plan.kernel == 1) return f32 ? hd::stage_k3_f32(s->plan.options, k3_role)
-                                      : hd::stage_k3_f64(s->plan.options, k3_role);
+  if (s->plan.kernel == 1) return f32 ? hd::stage_k3_f32(s->plan.options, k3_role, list)
+                                      : hd::stage_k3_f64(s->plan.options, k3_role, list);
   const int rd = s->plan.reg_dims, lds = s->plan.lds, n = s->n, sd = s->plan.split_dims,
             opt = s->plan.options, ld = s->plan.loop_dims;
   switch (s->d) {
-    case 2: return f32 ? hd::stage_d2_f32(n, rd, lds, sd, opt, ld) : hd::stage_d2_f64(n, rd, lds, sd, opt, ld);
-    case 3: return f32 ? hd::stage_d3_f32(n, rd, lds, sd, opt, ld) : hd::stage_d3_f64(n, rd, lds, sd, opt, ld);
-    case 4: return f32 ? hd::stage_d4_f32(n, rd, lds, sd, opt, ld) : hd::stage_d4_f64(n, rd, lds, sd, opt, ld);
-    case 5: return f32 ? hd::stage_d5_f32(n, rd, lds, sd, opt, ld) : hd::stage_d5_f64(n, rd, lds, sd, opt, ld);
-    case 6: return f32 ? hd::stage_d6_f32(n, rd, lds, sd, opt, ld) : hd::stage_d6_f64(n, rd, lds, sd, opt, ld);
+    case 2: return f32 ? hd::stage_d2_f32(n, rd, lds, sd, opt, ld, list) : hd::stage_d2_f64(n, rd, lds, sd, opt, ld, list);
+    case 3: return f32 ? hd::stage_d3_f32(n, rd, lds, sd, opt, ld, list) : hd::stage_d3_f64(n, rd, lds, sd, opt, ld, list);
+    case 4: return f32 ? hd::stage_d4_f32(n, rd, lds, sd, opt, ld, list) : hd::stage_d4_f64(n, rd, lds, sd, opt, ld, list);
+    case 5: return f32 ? hd::stage_d5_f32(n, rd, lds, sd, opt, ld, list) : hd::stage_d5_f64(n, rd, lds, sd, opt, ld, list);
+    case 6: return f32 ? hd::stage_d6_f32(n, rd, lds, sd, opt, ld, list) : hd::stage_d6_f64(n, rd, lds, sd, opt, ld, list);
   }
   return nullptr;
 }
@@ -279,8 +280,10 @@ bool split_compiled(int dx, int dv) {
          (dx == 3 && dv == 2) || (dx == 3 && dv == 3);
 }
 
+}  // namespace
+
 // Lets a kernel use up to 160 KiB of dynamic LDS, once per kernel entry.
-hipError_t allow_large_lds(const void *fn) {
+hipError_t hd::rt::allow_large_lds(const void *fn) {
   static std::mutex mu;
   static std::unordered_set<const void *> done;
   std::lock_guard<std::mutex> lock(mu);
@@ -295,6 +298,10 @@ hipError_t allow_large_lds(const void *fn) {
   if (e == hipSuccess) done.insert(fn);
   return e;
 }
+
+namespace {
+
+using hd::rt::allow_large_lds;
 
 // The nodal-space matrices of the Gauss-Legendre form at degree 3 (host,
 // FP64): Dt = B^-1 Dg B, G = B^-1 diag(g) B, B^-1 lift_s.
@@ -352,16 +359,25 @@ void k3mg_tables(const hd::GaussTables1D &g, hd::K3MGaussTables<P> *mt) {
   for (int q = 0; q < 4; ++q) mt->g[q] = kt.g[q];
 }
 
+}  // namespace
+
+namespace hd {
+namespace rt {
+
+// Kernel parameters, launch shape and k3 role of one operator application
+// (mode 0: out = L(in)) or fused RK stage (mode 1: in -> u_out) of s, as
+// launch_op issues it.
 template <typename P>
-hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, int mode,
-                    int stage, double dt, hipStream_t st) {
-  hd::StageParams<P> prm;
+void fill_stage(const hd_solver *s, const double *in, void *out, double *u_out, int mode, int stage,
+                double dt, hd::StageParams<P> *prm_out, hd::LaunchShape *ls_out, int *k3_role_out) {
+  hd::StageParams<P> &prm = *prm_out;
   // The sweep kernel (Gauss-Legendre quadrature or mapped cells) reads the
   // fields in their own form, not the specialised kernel's.
   const bool k3g = hd::rt::k3g_used(s), k3m = hd::rt::k3m_used(s), k3mg = hd::rt::k3mg_used(s);
   const bool sweep = (s->quad == 1 || s->mapped()) && !k3g && !k3m && !k3mg;
   fill_params<P>(s, &prm, sweep ? 0 : s->plan.kernel);
   const hd::LaunchShape ls = hd::rt::shape_of(s);
+  *ls_out = ls;
   prm.nblocks = ls.grid;
   prm.u_in = in;
   prm.mode = mode;
@@ -376,10 +392,6 @@ hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, in
     prm.rk_b = kRkB[stage];
     prm.dt = (P)dt;
   }
-  if (ls.grid == 0) return HD_OK;
-  if ((uint64_t)ls.grid * ls.block >= (uint64_t(1) << 32))
-    return fail(HD_ERR_UNSUPPORTED, "stage launch exceeds 2^32 work-items; use a plan with more "
-                                    "nodes per thread");
   // Variants of the 6D degree-3 kernel: the first stage reads no increment;
   // the late-increment variant serves the last stage (FP64) or every later
   // stage (FP32), where it measured faster than holding the increment
@@ -395,6 +407,31 @@ hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, in
   // of its boundary lanes, which the slab of its own XCD keeps in that L2:
   // 8.5 against 10.0 ms per FP64 stage at 8^6 with the window order.
   if (k3m) prm.xcd_remap = 1;
+  *k3_role_out = k3_role;
+}
+
+template void fill_stage<float>(const hd_solver *, const double *, void *, double *, int, int,
+                                double, hd::StageParams<float> *, hd::LaunchShape *, int *);
+template void fill_stage<double>(const hd_solver *, const double *, void *, double *, int, int,
+                                 double, hd::StageParams<double> *, hd::LaunchShape *, int *);
+
+}  // namespace rt
+}  // namespace hd
+
+namespace {
+
+template <typename P>
+hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, int mode,
+                    int stage, double dt, hipStream_t st) {
+  hd::StageParams<P> prm;
+  hd::LaunchShape ls;
+  int k3_role = 0;
+  hd::rt::fill_stage<P>(s, in, out, u_out, mode, stage, dt, &prm, &ls, &k3_role);
+  if (ls.grid == 0) return HD_OK;
+  if ((uint64_t)ls.grid * ls.block >= (uint64_t(1) << 32))
+    return fail(HD_ERR_UNSUPPORTED, "stage launch exceeds 2^32 work-items; use a plan with more "
+                                    "nodes per thread");
+  const bool k3g = hd::rt::k3g_used(s), k3m = hd::rt::k3m_used(s), k3mg = hd::rt::k3mg_used(s);
   const void *fn = hd::rt::stage_entry(s, k3_role);
   if (!fn) return fail(HD_ERR_HIP, "no compiled stage kernel for this plan");
   if (s->field_kind == 2) {
@@ -775,6 +812,12 @@ __global__ void stream_copy_tail(const double *src, double *dst, size_t begin, s
 // ===========================================================================
 // ABI
 // ===========================================================================
+
+hd_status hd::rt::enqueue_stage_of(hd_solver *s, int par, int stage, double dt, hipStream_t st) {
+  return s->prec == HD_FP32_OP_FP64_ACC
+             ? launch_op<float>(s, s->u(par), nullptr, s->u(1 - par), 1, stage, dt, st)
+             : launch_op<double>(s, s->u(par), nullptr, s->u(1 - par), 1, stage, dt, st);
+}
 
 hd_status hd::rt::enqueue_step(hd_solver *s, int par, double dt, hipStream_t st) {
   for (int stage = 0; stage < 5; ++stage, par = 1 - par) {

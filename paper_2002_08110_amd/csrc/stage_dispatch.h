@@ -46,94 +46,99 @@ constexpr bool loop_variant_ok() {
          (size_t)ipow(N, D - SD) * sizeof(P) <= kMaxLdsBytes;
 }
 
+// list != 0: the persistent work-list form of the same variant
+// (stage_list_kernel), which takes a ListParams<P> argument.
 template <int D, int N, int DX, int RD, typename P, bool LDS, int SD, int OPT, int LD>
-const void *variant_fn() {
+const void *variant_fn(int list) {
+  if (list) return reinterpret_cast<const void *>(&stage_list_kernel<D, N, DX, RD, P, LDS, SD, OPT, LD>);
   return reinterpret_cast<const void *>(&stage_kernel<D, N, DX, RD, P, LDS, SD, OPT, LD>);
 }
 
 template <int D, int N, int DX, int RD, typename P, bool LDS, int SD, int LD = 0>
-const void *resolve_opt(int opt) {
-  return (opt & kOptStream) ? variant_fn<D, N, DX, RD, P, LDS, SD, kOptStream, LD>()
-                            : variant_fn<D, N, DX, RD, P, LDS, SD, 0, LD>();
+const void *resolve_opt(int opt, int list) {
+  return (opt & kOptStream) ? variant_fn<D, N, DX, RD, P, LDS, SD, kOptStream, LD>(list)
+                            : variant_fn<D, N, DX, RD, P, LDS, SD, 0, LD>(list);
 }
 
 template <int D, int N, int DX, int RD, typename P, int SD>
-const void *resolve_loop(int lds, int opt) {
+const void *resolve_loop(int lds, int opt, int list) {
   if constexpr (loop_variant_ok<D, N, DX, RD, SD, P>())
-    return lds ? resolve_opt<D, N, DX, RD, P, true, SD, 1>(opt) : nullptr;
+    return lds ? resolve_opt<D, N, DX, RD, P, true, SD, 1>(opt, list) : nullptr;
   return nullptr;
 }
 
 template <int D, int N, int DX, int RD, typename P>
-const void *resolve_lds(int lds, int sd, int opt, int ld) {
+const void *resolve_lds(int lds, int sd, int opt, int ld, int list) {
   if (ld == 1) {
-    if (sd == 0) return resolve_loop<D, N, DX, RD, P, 0>(lds, opt);
-    if (sd == 1) return resolve_loop<D, N, DX, RD, P, 1>(lds, opt);
-    if (sd == 2) return resolve_loop<D, N, DX, RD, P, 2>(lds, opt);
+    if (sd == 0) return resolve_loop<D, N, DX, RD, P, 0>(lds, opt, list);
+    if (sd == 1) return resolve_loop<D, N, DX, RD, P, 1>(lds, opt, list);
+    if (sd == 2) return resolve_loop<D, N, DX, RD, P, 2>(lds, opt, list);
     return nullptr;
   }
   if (ld != 0) return nullptr;
   if (sd == 1) {
     if constexpr (split_variant_ok<D, N, DX, RD, 1, P>())
-      return lds ? resolve_opt<D, N, DX, RD, P, true, 1>(opt) : nullptr;
+      return lds ? resolve_opt<D, N, DX, RD, P, true, 1>(opt, list) : nullptr;
     return nullptr;
   }
   if (sd == 2) {
     if constexpr (split_variant_ok<D, N, DX, RD, 2, P>())
-      return lds ? resolve_opt<D, N, DX, RD, P, true, 2>(opt) : nullptr;
+      return lds ? resolve_opt<D, N, DX, RD, P, true, 2>(opt, list) : nullptr;
     return nullptr;
   }
   if (sd != 0) return nullptr;
   if (lds) {
-    if constexpr (lds_variant_ok<D, N, RD, P>()) return resolve_opt<D, N, DX, RD, P, true, 0>(opt);
+    if constexpr (lds_variant_ok<D, N, RD, P>()) return resolve_opt<D, N, DX, RD, P, true, 0>(opt, list);
     else return nullptr;
   }
-  return resolve_opt<D, N, DX, RD, P, false, 0>(opt);
+  return resolve_opt<D, N, DX, RD, P, false, 0>(opt, list);
 }
 
 template <int D, int N, int DX, typename P>
-const void *resolve_rd(int rd, int lds, int sd, int opt, int ld) {
+const void *resolve_rd(int rd, int lds, int sd, int opt, int ld, int list) {
   constexpr int DV = D - DX;
-  if (rd == 1) return resolve_lds<D, N, DX, 1, P>(lds, sd, opt, ld);
+  if (rd == 1) return resolve_lds<D, N, DX, 1, P>(lds, sd, opt, ld, list);
   if constexpr (DV >= 2) {
-    if (rd == 2) return resolve_lds<D, N, DX, 2, P>(lds, sd, opt, ld);
+    if (rd == 2) return resolve_lds<D, N, DX, 2, P>(lds, sd, opt, ld, list);
   }
   return nullptr;
 }
 
 template <int D, int DX, typename P>
-const void *resolve_n(int n, int rd, int lds, int sd, int opt, int ld) {
+const void *resolve_n(int n, int rd, int lds, int sd, int opt, int ld, int list) {
   switch (n) {
-    case 2: return resolve_rd<D, 2, DX, P>(rd, lds, sd, opt, ld);
-    case 3: return resolve_rd<D, 3, DX, P>(rd, lds, sd, opt, ld);
-    case 4: return resolve_rd<D, 4, DX, P>(rd, lds, sd, opt, ld);
-    case 5: return resolve_rd<D, 5, DX, P>(rd, lds, sd, opt, ld);
-    case 6: return resolve_rd<D, 6, DX, P>(rd, lds, sd, opt, ld);
+    case 2: return resolve_rd<D, 2, DX, P>(rd, lds, sd, opt, ld, list);
+    case 3: return resolve_rd<D, 3, DX, P>(rd, lds, sd, opt, ld, list);
+    case 4: return resolve_rd<D, 4, DX, P>(rd, lds, sd, opt, ld, list);
+    case 5: return resolve_rd<D, 5, DX, P>(rd, lds, sd, opt, ld, list);
+    case 6: return resolve_rd<D, 6, DX, P>(rd, lds, sd, opt, ld, list);
     default: return nullptr;
   }
 }
 
 // Defined in stage_dN_fP.hip (one per dimension and precision): the entry of
 // the generic kernel for n = degree + 1 nodes per dimension, rd register
-// dims, LDS mode, sd split dims, plan options opt and ld looped dims, or
-// nullptr if that variant is not compiled.
-const void *stage_d2_f64(int n, int rd, int lds, int sd, int opt, int ld);
-const void *stage_d3_f64(int n, int rd, int lds, int sd, int opt, int ld);
-const void *stage_d4_f64(int n, int rd, int lds, int sd, int opt, int ld);
-const void *stage_d5_f64(int n, int rd, int lds, int sd, int opt, int ld);
-const void *stage_d6_f64(int n, int rd, int lds, int sd, int opt, int ld);
-const void *stage_d2_f32(int n, int rd, int lds, int sd, int opt, int ld);
-const void *stage_d3_f32(int n, int rd, int lds, int sd, int opt, int ld);
-const void *stage_d4_f32(int n, int rd, int lds, int sd, int opt, int ld);
-const void *stage_d5_f32(int n, int rd, int lds, int sd, int opt, int ld);
-const void *stage_d6_f32(int n, int rd, int lds, int sd, int opt, int ld);
+// dims, LDS mode, sd split dims, plan options opt and ld looped dims (list:
+// its persistent work-list form), or nullptr if that variant is not
+// compiled.
+const void *stage_d2_f64(int n, int rd, int lds, int sd, int opt, int ld, int list = 0);
+const void *stage_d3_f64(int n, int rd, int lds, int sd, int opt, int ld, int list = 0);
+const void *stage_d4_f64(int n, int rd, int lds, int sd, int opt, int ld, int list = 0);
+const void *stage_d5_f64(int n, int rd, int lds, int sd, int opt, int ld, int list = 0);
+const void *stage_d6_f64(int n, int rd, int lds, int sd, int opt, int ld, int list = 0);
+const void *stage_d2_f32(int n, int rd, int lds, int sd, int opt, int ld, int list = 0);
+const void *stage_d3_f32(int n, int rd, int lds, int sd, int opt, int ld, int list = 0);
+const void *stage_d4_f32(int n, int rd, int lds, int sd, int opt, int ld, int list = 0);
+const void *stage_d5_f32(int n, int rd, int lds, int sd, int opt, int ld, int list = 0);
+const void *stage_d6_f32(int n, int rd, int lds, int sd, int opt, int ld, int list = 0);
 
 // Specialised kernel for d = 6 (3 x + 3 v), degree 3: one cell per
 // 256-thread workgroup (stage_k3.hip); options as in hd_plan.
 // role: 0 general (operator application, any stage), 1 first stage
 // (read_du == 0), 2 late increment (any stage after the first)
-const void *stage_k3_f64(int options, int role = 0);
-const void *stage_k3_f32(int options, int role = 0);
+// list != 0: the persistent work-list form (stage_k3_list_kernel).
+const void *stage_k3_f64(int options, int role = 0, int list = 0);
+const void *stage_k3_f32(int options, int role = 0, int list = 0);
 
 // Gauss-Legendre quadrature for d = 6 (3 x + 3 v), degree 3, Cartesian
 // cells, in the thread layout of the collocation kernel above

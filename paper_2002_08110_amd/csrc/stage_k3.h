@@ -85,9 +85,9 @@ constexpr int kOptKeepU64 = 2;
 
 // One workgroup's cell `cell` (lds_reuse as in stage_body) in stage role
 // ROLE; the first-stage role requires read_du == 0.
-template <typename P, int OPT, int ROLE>
-__device__ __forceinline__ void stage_k3_body(const StageParams<P> &prm, unsigned cell,
-                                              unsigned char *smem_raw, bool lds_reuse) {
+template <typename P, int OPT, int ROLE, typename PV = const StageParams<P>>
+__device__ __forceinline__ void stage_k3_body(PV &prm, unsigned cell, unsigned char *smem_raw,
+                                              bool lds_reuse, const int t) {
   constexpr bool NT = (OPT & kOptStream) != 0;
   constexpr bool KEEPU = (OPT & kOptKeepU64) != 0 && sizeof(P) == 4;
   constexpr bool EARLY_DU = ROLE == kK3General;  // increment loaded before the sweeps
@@ -95,7 +95,6 @@ __device__ __forceinline__ void stage_k3_body(const StageParams<P> &prm, unsigne
   constexpr int N = 4, ND = kK3Nodes, F = kK3Face;
   P *cellb = reinterpret_cast<P *>(smem_raw);
   P *faceb = cellb;  // layers of dims 1-4 first, then the cell
-  const int t = threadIdx.x;
   const int l = t & 63;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
   const int i1 = l & 3, i2 = (l >> 2) & 3, i3 = l >> 4;
@@ -393,7 +392,7 @@ __device__ __forceinline__ void stage_k3_body(const StageParams<P> &prm, unsigne
   }
   if (ANY_DU && prm.read_du) {
 #pragma unroll
-    for (int s = 0; s < 16; ++s) dv[s] = prm.rk_a * dv[s] + prm.dt * acc[s];
+    for (int s = 0; s < 16; ++s) dv[s] = rk_fma(prm.rk_a, dv[s], prm.dt * acc[s]);
   } else {
 #pragma unroll
     for (int s = 0; s < 16; ++s) dv[s] = prm.dt * acc[s];
@@ -410,7 +409,7 @@ __device__ __forceinline__ void stage_k3_body(const StageParams<P> &prm, unsigne
     if constexpr (sizeof(P) == sizeof(double)) uo = (double)u[s];
     else if constexpr (KEEPU) uo = ud[s];
     else uo = ucell[t + 256 * s];
-    const double un = uo + prm.rk_b * (double)dv[s];
+    const double un = rk_fma(prm.rk_b, (double)dv[s], uo);
     st_opt<NT>(uocell + t + 256 * s, un);
     mrow += prm.gw[s & 3] * un;
     if ((s & 3) == 3) {
@@ -428,7 +427,23 @@ __global__ void __launch_bounds__(256)
   extern __shared__ unsigned char smem_raw[];
   unsigned cell = blockIdx.x;
   if (prm.xcd_remap) cell = xcd_tile(cell, prm.nblocks);
-  stage_k3_body<P, OPT, ROLE>(prm, cell, smem_raw, false);
+  stage_k3_body<P, OPT, ROLE>(prm, cell, smem_raw, false, (int)threadIdx.x);
+}
+
+// Work-list form (as stage_list_kernel): workgroup `item` runs the cell of
+// the item's solve with that solve's parameters.
+template <typename P, int OPT, int ROLE>
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(k3_waves_per_eu<P, ROLE>(), k3_waves_per_eu<P, ROLE>())))
+    stage_k3_list_kernel(const ListParams<P> lp) {
+  extern __shared__ unsigned char smem_raw[];
+  const unsigned item = blockIdx.x;
+  const int slot = __builtin_amdgcn_readfirstlane(work_list_slot(lp.item0, lp.nslots, item));
+  const unsigned t0 = __builtin_amdgcn_readfirstlane(item - lp.item0[slot]);
+  ConstStageParams<P> &prm = lp.prm[slot];
+  if (t0 >= prm.nblocks) return;  // padding: the whole workgroup
+  const unsigned cell = prm.xcd_remap ? xcd_tile(t0, prm.nblocks) : t0;
+  stage_k3_body<P, OPT, ROLE, ConstStageParams<P>>(prm, cell, smem_raw, false, (int)threadIdx.x);
 }
 
 #undef Dm

@@ -36,6 +36,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "work_list.h"
+
 namespace hd {
 
 constexpr int kMaxN = 6;   // degree <= 5
@@ -113,6 +115,14 @@ __device__ __forceinline__ P to_p(double v) {
   return static_cast<P>(v);
 }
 
+// The low-storage RK update with one fixed rounding order: the increment
+// du' = fma(A_s, du, dt L) (dt L rounded first) and u' = fma(B_s, du', u).
+// Written out, a*b + c*d may be fused either way round, and two kernels
+// compiled from the same source (a solve's own launch and its batched
+// work-list form) could round differently.
+__device__ __forceinline__ float rk_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double rk_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // Plan option bit 0: non-temporal (streaming) loads and stores of the stage
 // increment and stores of the output solution, which are not re-read while
 // they could still be cached; keeps the cache for neighbour traces.
@@ -146,9 +156,10 @@ constexpr int stage_max_threads() {
 // slowest fast dimension one after another, so a unit of N^NF pencils runs
 // on N^(NF-1) threads: large units fit a workgroup, and the sweep along that
 // dimension still reads LDS.
-template <int D, int N, int DX, int RD, typename P, bool USE_LDS, int SD, int OPT, int LD = 0>
-__device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned tile, P *lds,
-                                           bool lds_reuse) {
+template <int D, int N, int DX, int RD, typename P, bool USE_LDS, int SD, int OPT, int LD = 0,
+          typename PV = const StageParams<P>>
+__device__ __forceinline__ void stage_body(PV &prm, unsigned tile, P *lds, bool lds_reuse,
+                                           const unsigned tid) {
   constexpr int DV = D - DX;
   static_assert(RD >= 1 && RD + SD <= DV, "register and split dims must be velocity dims");
   static_assert(SD == 0 || USE_LDS, "split dims need the LDS variant");
@@ -170,13 +181,13 @@ __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned t
 
   unsigned cell, t0, lc = 0, unit = 0;
   if constexpr (USE_LDS) {
-    lc = threadIdx.x / TT;
-    t0 = threadIdx.x - lc * TT;
+    lc = tid / TT;
+    t0 = tid - lc * TT;
     const unsigned U = tile * prm.cells_per_wg + lc;
     cell = U / NU;
     unit = U - cell * NU;
   } else {
-    const uint64_t p = (uint64_t)tile * blockDim.x + threadIdx.x;
+    const uint64_t p = (uint64_t)tile * blockDim.x + tid;
     cell = (unsigned)(p / T);
     t0 = (unsigned)(p - (uint64_t)cell * T);
   }
@@ -482,7 +493,7 @@ __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned t
       for (int s = 0; s < NS; ++s) dv[s] = ld_opt<NT>(prm.du + base + (uint64_t)s * SST);
     }
 #pragma unroll
-    for (int s = 0; s < NS; ++s) dv[s] = prm.rk_a * dv[s] + prm.dt * acc[s];
+    for (int s = 0; s < NS; ++s) dv[s] = rk_fma(prm.rk_a, dv[s], prm.dt * acc[s]);
   } else {
 #pragma unroll
     for (int s = 0; s < NS; ++s) dv[s] = prm.dt * acc[s];
@@ -498,7 +509,7 @@ __device__ __forceinline__ void stage_body(const StageParams<P> &prm, unsigned t
     if constexpr (sizeof(P) == sizeof(double)) uo = (double)u[s];
     else if constexpr (KEEPU) uo = u64[s];
     else uo = prm.u_in[base + (uint64_t)s * SST];
-    st_opt<NT>(prm.u_out + base + (uint64_t)s * SST, uo + prm.rk_b * (double)dv[s]);
+    st_opt<NT>(prm.u_out + base + (uint64_t)s * SST, rk_fma(prm.rk_b, (double)dv[s], uo));
   }
   };  // pencil
   if constexpr (LD == 0) {
@@ -520,7 +531,44 @@ __global__ void __launch_bounds__((stage_max_threads<D, N, RD, USE_LDS, SD, LD>(
   unsigned tile = blockIdx.x;
   if (prm.xcd_remap) tile = xcd_tile(tile, prm.nblocks);
   stage_body<D, N, DX, RD, P, USE_LDS, SD, OPT, LD>(prm, tile, reinterpret_cast<P *>(smem_raw),
-                                                    false);
+                                                    false, threadIdx.x);
+}
+
+// Work list of a batched launch (work_list.h): the solves of one launch
+// group (one compiled variant and launch shape) in slots 0..nslots-1, a
+// solve's tile count in its StageParams::nblocks.
+// A solve's parameters as the work-list kernels read them: in the constant
+// address space, so the loads are scalar and invariant, like those of a
+// kernel argument.
+template <typename P>
+using ConstStageParams = const __attribute__((address_space(4))) StageParams<P>;
+
+template <typename P>
+struct ListParams {
+  ConstStageParams<P> *prm;  // one per slot
+  const uint32_t *item0;     // nslots + 1 entries (work_list.h)
+  int nslots;
+  unsigned nitems;           // item0[nslots] = the grid
+};
+
+// Work-list form of stage_kernel: one launch covers the tiles of every solve
+// of a group, workgroup `item` running the stage body of the item's solve
+// and tile with that solve's parameters. (A form in which each workgroup
+// loops over items holds the body's registers across iterations: the
+// compiler gives it fewer waves per SIMD than stage_kernel for a quarter of
+// the variants, so the work items are workgroups here.)
+template <int D, int N, int DX, int RD, typename P, bool USE_LDS, int SD, int OPT, int LD = 0>
+__global__ void __launch_bounds__((stage_max_threads<D, N, RD, USE_LDS, SD, LD>()))
+    stage_list_kernel(const ListParams<P> lp) {
+  extern __shared__ unsigned char smem_raw[];
+  const unsigned item = blockIdx.x;
+  const int slot = __builtin_amdgcn_readfirstlane(work_list_slot(lp.item0, lp.nslots, item));
+  const unsigned t0 = __builtin_amdgcn_readfirstlane(item - lp.item0[slot]);
+  ConstStageParams<P> &prm = lp.prm[slot];
+  if (t0 >= prm.nblocks) return;  // padding: the whole workgroup
+  const unsigned tile = prm.xcd_remap ? xcd_tile(t0, prm.nblocks) : t0;
+  stage_body<D, N, DX, RD, P, USE_LDS, SD, OPT, LD, ConstStageParams<P>>(
+      prm, tile, reinterpret_cast<P *>(smem_raw), false, threadIdx.x);
 }
 
 }  // namespace hd

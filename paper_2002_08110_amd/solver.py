@@ -282,8 +282,8 @@ class Solver:
 
 class Batch:
     """hd_batch over bound Solvers (any d, degree, size, precision, plan):
-    one hipGraph replay per step advances every active solve, each solve's
-    own stage launches on parallel graph branches."""
+    one hipGraph replay per step advances every active solve; per RK stage,
+    one work-list launch per kernel-variant group (hd_batch_step)."""
 
     def __init__(self, solvers):
         self.lib = _hd.load()
@@ -298,6 +298,13 @@ class Batch:
         dt = (ctypes.c_double * n)(*[float(x) for x in dts])
         act = None if active is None else (ctypes.c_int * n)(*[int(bool(a)) for a in active])
         check(self.lib.hd_batch_step(self.h, dt, act, _stream(stream)))
+
+    def launch_counts(self):
+        """(work-list launches, single-solve stage launches) of the most
+        recently captured step."""
+        a, b = ctypes.c_int(), ctypes.c_int()
+        check(self.lib.hd_batch_launch_counts(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:

@@ -70,6 +70,10 @@ CONFIG_4D = phase_space_case("4d_phase_16^4_k3", 2, 2, [16] * 4, 3, 20)
 CONFIG_6D = phase_space_case("6d_phase_8^6_k3", 3, 3, [8] * 6, 3, 10)
 # Its reduced rerun for the FP32-vs-FP64 error: 4^6 cells (16.8M DoFs).
 CONFIG_6D_SMALL = phase_space_case("6d_phase_4^6_k3", 3, 3, [4] * 6, 3, 10)
+# The same phase-space workload at degrees 4 and 5 (about 1.6e8 / 1.9e8 DoFs):
+# the degrees that dominate the batched mix and the served requests.
+CONFIG_6D_K4 = phase_space_case("6d_phase_5^4x4^2_k4", 3, 3, [5, 5, 5, 5, 4, 4], 4, 10)
+CONFIG_6D_K5 = phase_space_case("6d_phase_4^6_k5", 3, 3, [4] * 6, 5, 10)
 
 
 def random_state(n, seed):

@@ -1,0 +1,40 @@
+// Host stand-in for the HIP device environment the stage kernels use, so
+// that tests can compile the kernel sources for the CPU and run them under
+// AddressSanitizer (tests/native/emu_stage.cpp). Test harness only: the
+// library itself is always built with hipcc for gfx950.
+//
+// A workgroup runs as blockDim.x host threads; __syncthreads is a barrier
+// over them. Workgroups run one after another, so the dynamic LDS
+// (hd::smem_raw) is one host array, poisoned beyond the launch's size.
+// Wave-level builtins are given their uniform-value meaning.
+#pragma once
+
+#include <stdint.h>
+#include <stddef.h>
+#include <string.h>
+
+#define __global__
+#define __device__
+#define __host__
+#define __forceinline__ inline
+#define __launch_bounds__(...)
+#define __shared__
+
+struct emu_dim3 {
+  unsigned x = 0, y = 0, z = 0;
+};
+extern thread_local emu_dim3 threadIdx, blockIdx;
+extern emu_dim3 blockDim, gridDim;
+
+void emu_syncthreads();
+#define __syncthreads() emu_syncthreads()
+#define __builtin_amdgcn_sched_barrier(x) ((void)0)
+#define __builtin_amdgcn_readfirstlane(x) (x)
+
+typedef void *hipStream_t;
+typedef void *hipGraphExec_t;
+typedef void *hipEvent_t;
+typedef int hipError_t;
+struct double2 {
+  double x, y;
+};

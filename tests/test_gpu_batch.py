@@ -1,8 +1,9 @@
-"""Batched stepping (one hipGraph per step for all active solves): each solve
-in the mix equals the same solve stepped alone (bitwise: the same kernels
-with the same parameters) and the oracle (FP64, 1e-12), whatever the plans
-and precisions in the mix; inactive solves stay untouched, and per-solve
-time steps, outside steps and plan changes are honoured."""
+"""Batched stepping (one hipGraph per step for all active solves; per RK
+stage one work-list launch per kernel-variant group): each solve in the mix
+equals the same solve stepped alone (bitwise: the same stage body with the
+same parameters) and the oracle (FP64, 1e-12), whatever the plans and
+precisions in the mix; inactive solves stay untouched, and per-solve time
+steps, outside steps and plan changes are honoured."""
 import numpy as np
 import pytest
 
@@ -36,12 +37,14 @@ def _plan_for(i, case, precision, vary):
     return plans[(7 * i) % len(plans)]
 
 
-# An earlier batched design (persistent work-list kernels per launch variant)
-# faulted the GPU on the plan-varied mix below; its cause was not found, and
-# that design was removed. These parameter sets stay skipped; the current
-# design is covered by test_batch_mixed_plans_and_precisions.
-_LIST_FAULT = pytest.mark.skip(reason="faulted under the removed work-list batch design; "
-                                      "cause not found")
+# An earlier batched design (persistent work-list kernels per launch variant,
+# each workgroup looping over items) faulted the GPU on the plan-varied mix
+# below; its code was not kept and the cause was not found. These parameter
+# sets stay off the GPU; plan-varied mixes under the current design are
+# covered by test_batch_mixed_plans_and_precisions and
+# test_batch_groups_of_many_solves.
+_LIST_FAULT = pytest.mark.skip(reason="faulted under an earlier work-list batch design whose "
+                                      "code was not kept; cause not found")
 
 
 @pytest.mark.parametrize("precision,vary", [
@@ -65,6 +68,8 @@ def test_batch_equals_alone_and_oracle(precision, vary):
     steps = 3
     for _ in range(steps):
         B.step(dts)
+    nlist, nown = B.launch_counts()
+    assert nlist >= 5 and nlist + nown <= 5 * len(cases)  # work-list launches are used
     for a, dt in zip(alone, dts):
         a.rk_step(dt, steps)
     torch.cuda.synchronize()
@@ -172,3 +177,52 @@ def test_batch_rejects_unbound_and_duplicates():
         Batch([a, u])
     with pytest.raises(HDError):
         Batch([a, a])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_groups_of_many_solves(precision):
+    # Many solves per kernel-variant group (same d, degree and plan, uneven
+    # meshes and fields): each group is one work-list launch per stage with
+    # many slots, every slot's tiles at their own offsets. Includes 6D
+    # degree 3 (the specialised kernel's work-list form, all three stage
+    # variants) and slab/looped-pencil variants of 5D degree 5.
+    from paper_2002_08110_amd.solver import Batch
+    rng = np.random.default_rng(7 if precision == "fp64" else 8)
+    cases = []
+    for i in range(6):
+        cells = [int(x) for x in rng.integers(1, 5, 4)]
+        cases.append(W.phase_space_case("g4_%d" % i, 2, 2, cells, 3, 2))
+    for i in range(4):
+        cells = [int(x) for x in rng.integers(1, 3, 6)]
+        cases.append(W.phase_space_case("g6_%d" % i, 3, 3, cells, 3, 2))
+    for i in range(3):
+        cells = [int(x) for x in rng.integers(1, 3, 3)]
+        cases.append(W.Case("g3_%d" % i, 2, 1, cells, [0.0] * 3, [1.0] * 3, 5, "constant",
+                            a=list(rng.uniform(-1, 1, 3)), steps=2))
+    for i in range(2):
+        cells = [1, 2, 1, 1, 2] if i == 0 else [2, 1, 1, 2, 1]
+        cases.append(W.Case("g5_%d" % i, 3, 2, cells, [0.0] * 5, [1.0] * 5, 5, "constant",
+                            a=list(rng.uniform(-1, 1, 5)), steps=2))
+    states = [W.random_state(c.ndofs, seed=300 + i) for i, c in enumerate(cases)]
+    mixed = [gpu_solver(c, precision) for c in cases]
+    alone = [gpu_solver(c, precision) for c in cases]
+    for s, a, u in zip(mixed, alone, states):
+        s.set_state(u)
+        a.set_state(u)
+    dts = [s.stable_dt(0.2) for s in mixed]
+    B = Batch(mixed)
+    for _ in range(3):
+        B.step(dts)
+    nlist, nown = B.launch_counts()
+    print("work-list launches %d, single-solve launches %d per step" % (nlist, nown))
+    assert nlist >= 5
+    for a, dt in zip(alone, dts):
+        a.rk_step(dt, 3)
+    torch.cuda.synchronize()
+    for i, (c, s, a, u, dt) in enumerate(zip(cases, mixed, alone, states, dts)):
+        got = s.get_state()
+        assert np.array_equal(got, a.get_state()), (i, c.name)
+        if precision == "fp64" and c.d <= 4:
+            ref = oracle_problem(c).rk_steps(u, dt, 3)
+            assert rel_l2(got, ref) <= TOL_FP64, (i, c.name)
+    B.close()
