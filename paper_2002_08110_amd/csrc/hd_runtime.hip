@@ -381,6 +381,9 @@ void fill_stage(const hd_solver *s, const double *in, void *out, double *u_out, 
   prm.nblocks = ls.grid;
   prm.u_in = in;
   prm.mode = mode;
+  // The increment buffer is always a valid address (operator applications
+  // neither read nor write it; the 6D degree-3 kernel forms its address).
+  prm.du = reinterpret_cast<P *>(s->du());
   if (mode == 0) {
     prm.out = reinterpret_cast<P *>(out);
   } else {

@@ -6,7 +6,9 @@
 // A workgroup runs as blockDim.x host threads; __syncthreads is a barrier
 // over them. Workgroups run one after another, so the dynamic LDS
 // (hd::smem_raw) is one host array, poisoned beyond the launch's size.
-// Wave-level builtins are given their uniform-value meaning.
+// readfirstlane is given its uniform-value meaning; cross-lane moves (DPP
+// quad permutations and row rotations) exchange values between the host
+// threads of one 64-lane wave.
 #pragma once
 
 #include <stdint.h>
@@ -18,6 +20,7 @@
 #define __host__
 #define __forceinline__ inline
 #define __launch_bounds__(...)
+#define amdgpu_waves_per_eu(...)
 #define __shared__
 
 struct emu_dim3 {
@@ -27,7 +30,9 @@ extern thread_local emu_dim3 threadIdx, blockIdx;
 extern emu_dim3 blockDim, gridDim;
 
 void emu_syncthreads();
+int emu_mov_dpp(int v, int ctrl);
 #define __syncthreads() emu_syncthreads()
+#define __builtin_amdgcn_mov_dpp(v, ctrl, row_mask, bank_mask, bound_ctrl) emu_mov_dpp((v), (ctrl))
 #define __builtin_amdgcn_sched_barrier(x) ((void)0)
 #define __builtin_amdgcn_readfirstlane(x) (x)
 

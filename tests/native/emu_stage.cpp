@@ -17,7 +17,8 @@
 // DIR/out.bin (operator mode).
 #include "hip/hip_runtime.h"
 
-#include <condition_variable>
+#include <atomic>
+#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <fstream>
@@ -28,6 +29,7 @@
 #include <vector>
 
 #include "hd_internal.h"
+#include "stage_k3.h"
 #include "work_list.h"
 
 thread_local emu_dim3 threadIdx, blockIdx;
@@ -39,48 +41,64 @@ alignas(256) unsigned char smem_raw[160 * 1024];
 
 namespace {
 
-// A reusable barrier over the threads of one workgroup; a thread that
-// returns from the kernel leaves it.
+// A reusable barrier over the threads of one workgroup (or wave); a thread
+// that returns from the kernel leaves it. Waiting threads yield the CPU
+// (there are far more of them than cores).
 struct Barrier {
   std::mutex mu;
-  std::condition_variable cv;
   int expected = 0, arrived = 0;
-  uint64_t gen = 0;
+  std::atomic<uint64_t> gen{0};
   void arrive_and_wait() {
-    std::unique_lock<std::mutex> lk(mu);
-    const uint64_t g = gen;
-    if (++arrived == expected) {
-      arrived = 0;
-      ++gen;
-      cv.notify_all();
-      return;
+    uint64_t g;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      g = gen.load();
+      if (++arrived == expected) {
+        arrived = 0;
+        gen.store(g + 1);
+        return;
+      }
     }
-    if (!cv.wait_for(lk, std::chrono::seconds(60), [&] { return gen != g; })) {
-      std::fprintf(stderr, "barrier timeout (divergent __syncthreads)\n");
-      std::abort();
+    const auto t0 = std::chrono::steady_clock::now();
+    while (gen.load() == g) {
+      std::this_thread::yield();
+      if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(120)) {
+        std::fprintf(stderr, "barrier timeout (divergent barrier or cross-lane move)\n");
+        std::abort();
+      }
     }
   }
   void leave() {
-    std::unique_lock<std::mutex> lk(mu);
+    std::lock_guard<std::mutex> lk(mu);
     --expected;
     if (arrived == expected && arrived > 0) {
       arrived = 0;
-      ++gen;
-      cv.notify_all();
+      gen.store(gen.load() + 1);
     }
   }
 };
 Barrier *g_bar = nullptr;
 
+// Per wave of a workgroup: a barrier over its threads and an exchange
+// buffer for cross-lane moves.
+struct Wave {
+  Barrier bar;
+  int buf[64];
+  bool live[64];
+};
+std::vector<Wave> *g_waves = nullptr;
+
 // The workgroups of a grid, one after another, each on `block` host
 // threads that stay alive across workgroups (a gate between workgroups
-// resets the LDS and the in-kernel barrier).
+// resets the LDS and the barriers).
 template <typename F>
 void run_grid(unsigned grid, unsigned block, size_t shmem, F kernel) {
   gridDim.x = grid;
   blockDim.x = block;
   Barrier bar, gate;
   gate.expected = (int)block;
+  const unsigned nw = (block + 63) / 64;
+  std::vector<Wave> waves(nw);
   std::mutex gmu;
   int at_gate = 0;
   auto fresh_block = [&] {
@@ -90,9 +108,15 @@ void run_grid(unsigned grid, unsigned block, size_t shmem, F kernel) {
     ASAN_POISON_MEMORY_REGION(hd::smem_raw + shmem, sizeof(hd::smem_raw) - shmem);
     bar.expected = (int)block;
     bar.arrived = 0;
+    for (unsigned w = 0; w < nw; ++w) {
+      waves[w].bar.expected = (int)std::min(64u, block - 64 * w);
+      waves[w].bar.arrived = 0;
+      for (int l = 0; l < 64; ++l) waves[w].live[l] = 64 * w + l < block;
+    }
   };
   fresh_block();
   g_bar = &bar;
+  g_waves = &waves;
   std::vector<std::thread> th;
   th.reserve(block);
   for (unsigned t = 0; t < block; ++t)
@@ -101,6 +125,12 @@ void run_grid(unsigned grid, unsigned block, size_t shmem, F kernel) {
       for (unsigned b = 0; b < grid; ++b) {
         blockIdx.x = b;
         kernel();
+        {
+          Wave &wv = waves[t / 64];
+          std::lock_guard<std::mutex> lk(wv.bar.mu);
+          wv.live[t % 64] = false;
+        }
+        waves[t / 64].bar.leave();
         bar.leave();
         {
           // The last thread of this workgroup prepares the next one.
@@ -137,6 +167,34 @@ void write_bin(const std::string &path, const T *p, size_t n) {
 }  // namespace
 
 void emu_syncthreads() { g_bar->arrive_and_wait(); }
+
+// DPP move within a 64-lane wave: quad_perm (ctrl 0x00-0xff: lane p reads
+// lane 4*(p/4) + sel_(p%4)) and row_ror:n (0x121-0x12f: lane p of a 16-lane
+// row reads lane (p - n) mod 16 of that row). A source lane that has left
+// the kernel is an error.
+int emu_mov_dpp(int v, int ctrl) {
+  const unsigned t = threadIdx.x, lane = t % 64;
+  Wave &wv = (*g_waves)[t / 64];
+  wv.buf[lane] = v;
+  wv.bar.arrive_and_wait();
+  unsigned src;
+  if (ctrl >= 0 && ctrl <= 0xff) {
+    src = (lane & ~3u) | ((unsigned)(ctrl >> (2 * (lane & 3))) & 3u);
+  } else if (ctrl >= 0x121 && ctrl <= 0x12f) {
+    const unsigned n = (unsigned)ctrl & 15u;
+    src = (lane & ~15u) | ((lane - n) & 15u);
+  } else {
+    std::fprintf(stderr, "unsupported DPP control 0x%x\n", ctrl);
+    std::abort();
+  }
+  if (!wv.live[src]) {
+    std::fprintf(stderr, "DPP move reads lane %u, which has left the kernel\n", src);
+    std::abort();
+  }
+  const int r = wv.buf[src];
+  wv.bar.arrive_and_wait();
+  return r;
+}
 
 int main(int argc, char **argv) {
   using P = EMU_P;
@@ -189,13 +247,24 @@ int main(int argc, char **argv) {
   for (int j = 0; j < DX; ++j) nxnodes *= s.mesh.cells[j] * N;
   const size_t nE = (size_t)(nxnodes * DX);
 
+#ifdef EMU_K3
+  // The 6D degree-3 kernel: one cell per 256-thread workgroup.
+  constexpr bool K3 = true;
+#else
+  constexpr bool K3 = false;
+#endif
+  s.plan.kernel = K3 ? 1 : 0;
   // Launch shape of the generic kernel under this plan (as the library's).
   int64_t T = 1, per_cell = 1;
   for (int j = 0; j < D - RD - SD - LD; ++j) T *= N;
   for (int j = 0; j < SD; ++j) per_cell *= N;
   unsigned grid, block;
   size_t shmem;
-  if (LDS) {
+  if (K3) {
+    grid = (unsigned)s.ncells;
+    block = 256;
+    shmem = 4096 * sizeof(P);
+  } else if (LDS) {
     const int64_t units = s.ncells * per_cell;
     grid = (unsigned)((units + cpw - 1) / cpw);
     block = (unsigned)(cpw * T);
@@ -210,6 +279,18 @@ int main(int argc, char **argv) {
   const std::vector<P> du0 = read_bin<P>(dir + "/du.bin", nd);
   std::vector<P> E;
   if (s.field_kind == 1) E = read_bin<P>(dir + "/E.bin", nE);
+  else if (K3) {
+    // The 6D degree-3 kernel reads a constant a_v from the E table.
+    E.resize(nE);
+    for (size_t i = 0; i < nE; ++i) E[i] = (P)s.a_const[DX + (int)(i % DX)];
+  }
+  // Stage variant of the 6D degree-3 kernel and its cell order (as the
+  // library chooses them): first stage, late increment (FP32 after the
+  // first stage, FP64 last stage) or general; the FP64 first and late
+  // variants take one slab of cells per XCD.
+  const bool f32 = sizeof(P) == 4;
+  const int role = mode != 1 ? 0 : (stage == 0 ? 1 : (f32 || stage == 4 ? 2 : 0));
+  if (K3 && !f32 && role != 0) xcd = 1;
 
   struct Bufs {
     std::vector<double> u, uo;
@@ -229,11 +310,13 @@ int main(int argc, char **argv) {
     // A constant field passes its a_v in the E table (the kernel reads
     // prm.a_const for the generic variant; the table is unused then).
     hd::StageParams<P> prm;
-    hd::rt::fill_params<P>(&s, &prm, 0);
+    hd::rt::fill_params<P>(&s, &prm, K3 ? 1 : 0);
+    prm.xcd_remap = xcd;
     prm.E = b.E.data();
     prm.nblocks = grid;
     prm.u_in = b.u.data();
     prm.mode = mode;
+    prm.du = b.du.data();  // as the library passes it, also to operator applications
     if (mode == 0) {
       prm.out = b.out.data();
     } else {
@@ -252,7 +335,13 @@ int main(int argc, char **argv) {
   Bufs own = make();
   const hd::StageParams<P> prm_own = params(own);
   run_grid(grid, block, shmem, [&] {
+#ifdef EMU_K3
+    if (role == 1) hd::stage_k3_kernel<P, EMU_OPT, hd::kK3First>(prm_own);
+    else if (role == 2) hd::stage_k3_kernel<P, EMU_OPT, hd::kK3Last>(prm_own);
+    else hd::stage_k3_kernel<P, EMU_OPT, hd::kK3General>(prm_own);
+#else
     hd::stage_kernel<D, N, DX, RD, P, LDS, SD, EMU_OPT, LD>(prm_own);
+#endif
   });
 
   // The work-list form: the solve and a copy with its own buffers.
@@ -269,7 +358,15 @@ int main(int argc, char **argv) {
   lp.item0 = item0.data();
   lp.nslots = 2;
   lp.nitems = item0.back();
-  run_grid(lp.nitems, block, shmem, [&] { hd::stage_list_kernel<D, N, DX, RD, P, LDS, SD, EMU_OPT, LD>(lp); });
+  run_grid(lp.nitems, block, shmem, [&] {
+#ifdef EMU_K3
+    if (role == 1) hd::stage_k3_list_kernel<P, EMU_OPT, hd::kK3First>(lp);
+    else if (role == 2) hd::stage_k3_list_kernel<P, EMU_OPT, hd::kK3Last>(lp);
+    else hd::stage_k3_list_kernel<P, EMU_OPT, hd::kK3General>(lp);
+#else
+    hd::stage_list_kernel<D, N, DX, RD, P, LDS, SD, EMU_OPT, LD>(lp);
+#endif
+  });
 
   auto same = [&](const Bufs &x, const Bufs &y) {
     if (mode == 0) return std::memcmp(x.out.data(), y.out.data(), nd * sizeof(P)) == 0;

@@ -226,3 +226,39 @@ def test_batch_groups_of_many_solves(precision):
             ref = oracle_problem(c).rk_steps(u, dt, 3)
             assert rel_l2(got, ref) <= TOL_FP64, (i, c.name)
     B.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_at_the_headline_size_equals_alone(precision):
+    # The 6D 8^6 degree-3 solve (1.07e9 DoFs, 262144 work items per stage)
+    # batched with a small 4D solve: after one step each equals itself
+    # stepped alone, bitwise (compared on the device).
+    from paper_2002_08110_amd.solver import Batch
+    big = W.CONFIG_6D
+    small = W.phase_space_case("s4", 2, 2, [3, 2, 4, 3], 3, 1)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(99)
+    outs = []
+    for batched in (True, False):
+        sb, ss = gpu_solver(big, precision), gpu_solver(small, precision)
+        g.manual_seed(99)
+        sb.set_state(torch.randn(sb.ndofs, dtype=torch.float64, device="cuda", generator=g))
+        ss.set_state(torch.randn(ss.ndofs, dtype=torch.float64, device="cuda", generator=g))
+        dts = [sb.stable_dt(0.2), ss.stable_dt(0.2)]
+        if batched:
+            B = Batch([sb, ss])
+            B.step(dts)
+            assert B.launch_counts()[0] >= 5
+        else:
+            sb.rk_step(dts[0])
+            ss.rk_step(dts[1])
+        torch.cuda.synchronize()
+        outs.append((sb.state_tensor().clone(), ss.state_tensor().clone()))
+        if batched:
+            B.close()
+        sb.close()
+        ss.close()
+        del sb, ss
+        torch.cuda.empty_cache()
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert torch.equal(outs[0][1], outs[1][1])

@@ -9,8 +9,9 @@ kept off the GPU: an earlier work-list design faulted on them), in both
 precisions, in operator mode and in each of the five stage variants. For each
 case: no access leaves its buffer or the launch's dynamic LDS, the work-list
 form (two slots) equals the own launch bitwise, and the result matches the
-oracle (FP64 within 1e-12 relative L2; FP32 within 2e-6). The 6D degree-3
-kernel (cross-lane moves) is not emulated here.
+oracle (FP64 within 1e-12 relative L2; FP32 within 2e-6). Among them is the
+6D degree-3 kernel (cross-lane moves exchanged between the threads of a
+64-lane wave) in each of its three stage variants.
 """
 import concurrent.futures as cf
 import os
@@ -34,7 +35,12 @@ SRC = os.path.join(ROOT, "tests", "native", "emu_stage.cpp")
 
 
 def _variant(case, plan, precision):
-    return dict(D=case.d, N=case.degree + 1, DX=case.dim_x, RD=plan["reg_dims"],
+    if plan.get("kernel", 0) == 1:
+        # The 6D degree-3 kernel: FP64 uses option bit 0 only, FP32 both bits.
+        opt = plan.get("options", 0) & (3 if precision == "fp32" else 1)
+        return dict(K3=1, D=6, N=4, DX=3, RD=2, P="float" if precision == "fp32" else "double",
+                    LDS="true", SD=0, OPT=opt, LD=0)
+    return dict(K3=0, D=case.d, N=case.degree + 1, DX=case.dim_x, RD=plan["reg_dims"],
                 P="float" if precision == "fp32" else "double",
                 LDS="true" if plan["lds"] else "false", SD=plan.get("split_dims", 0),
                 OPT=plan.get("options", 0) & 1, LD=plan.get("loop_dims", 0))
@@ -47,8 +53,6 @@ def _cases():
             case = make_case(i, *m)
             plans = all_plans(case, precision)
             plan = plans[(7 * i) % len(plans)]
-            if plan.get("kernel", 0) == 1:
-                continue
             out.append((precision, i, case, plan))
     return out
 
@@ -73,7 +77,8 @@ def binaries(tmp_path_factory):
                "-fno-sanitize-recover=all", "-I" + os.path.join(ROOT, "tests", "native", "emu"),
                "-I" + os.path.join(ROOT, "paper_2002_08110_amd", "csrc"),
                "-I" + os.path.join(ROOT, "include")]
-        cmd += ["-DEMU_%s=%s" % (k, v[k]) for k in sorted(v)] + [SRC, "-o", exe]
+        cmd += ["-DEMU_%s=%s" % (k, v[k]) for k in sorted(v) if k != "K3"]
+        cmd += (["-DEMU_K3"] if v["K3"] else []) + [SRC, "-o", exe]
         subprocess.run(cmd, check=True, capture_output=True)
         return exe
 
