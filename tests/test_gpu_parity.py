@@ -163,7 +163,7 @@ def test_constant_field_rk_matches_oracle(d, k, cells):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("d,k,cells", [(6, 3, [2, 1, 3, 2, 1, 2]), (4, 2, [3, 2, 2, 3]),
                                        (5, 4, [1, 2, 1, 2, 2]), (6, 3, [1, 2, 1, 1, 3, 1]),
-                                       (6, 3, [1, 2, 1, 2, 4, 1])])
+                                       (6, 3, [1, 2, 1, 2, 4, 1]), (6, 3, [2, 1, 1, 2, 2, 2])])
 def test_rk_steps_match_oracle_for_every_plan(precision, d, k, cells):
     # Every launch plan the autotuner may pick, in stage mode (the fused RK
     # update, streaming options of the 6D degree-3 kernel included).
