@@ -81,7 +81,12 @@ typedef struct hd_batch hd_batch;    /* opaque */
  *  xcd_remap:  1 = map consecutive cell tiles to the same XCD.
  *  reg_dims:   number of slowest dimensions whose lines a thread keeps in
  *              registers (1 or 2; at most dim_v).
- *  kernel:     0 = the generic kernel (the fields above apply); 1 = the
+ *  kernel:     0 = the generic kernel (the fields above apply); 2 = the
+ *              dimension-split passes for d = 6 (3 x + 3 v) and d = 5 (3 x +
+ *              2 v) at degrees 4 and 5 with collocation on Cartesian cells:
+ *              two launches per stage, the x-dimension terms of whole node
+ *              rows, then the velocity terms of column blocks with the RK
+ *              update (only xcd_remap and options bit 0 apply); 1 = the
  *              kernel specialised for d = 6 (3 x + 3 v) at degree 3, one cell
  *              per 256-thread workgroup (only xcd_remap and options apply;
  *              its FP64 first- and last-stage variants always take one slab
@@ -91,7 +96,7 @@ typedef struct hd_batch hd_batch;    /* opaque */
  *              mapped Gauss-Legendre; xcd_remap and the streaming stores
  *              apply, except that mapped collocation always takes one slab
  *              per XCD).
- *  options:    bit 0 (both kernels): non-temporal (streaming) loads and
+ *  options:    bit 0 (every kernel): non-temporal (streaming) loads and
  *              stores of the stage increment du and stores of the output
  *              solution, so they do not displace cached neighbour data;
  *              bit 1 (kernel 1, FP32 only): keep the FP64 input solution in

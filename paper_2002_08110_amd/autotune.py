@@ -3,7 +3,8 @@
 For a representative mesh it times every valid plan - generic kernel with
 one or two register dimensions, LDS or global line reads, cells per
 workgroup, XCD-aware tile order; the 6D degree-3 kernel with its streaming
-options - over full RK steps' worth of stage launches, and records the
+options; the dimension-split passes at degrees 4 and 5 (d = 5, 6) - over
+full RK steps' worth of stage launches, and records the
 fastest in a JSON cache keyed by (GPU architecture, d, k, precision). A
 Solver picks its plan from the cache with `apply_tuned_plan`.
 
@@ -80,6 +81,11 @@ def candidate_plans(d, k, dim_v, precision):
     generic = [p for p in plans if p["kernel"] == 0]
     for p in generic:  # the streaming option of the generic kernel
         plans.append(dict(p, options=1))
+    if dim_v in (2, 3) and d - dim_v == 3 and k in (4, 5):
+        # the dimension-split passes (x terms, then v terms and the update)
+        for xcd in (0, 1):
+            for opt in (0, 1):
+                plans.append(dict(kernel=2, options=opt, xcd_remap=xcd, split_dims=0))
     full = dict(lds=0, cells_per_wg=1, wg_size=256, xcd_remap=0, reg_dims=1, kernel=0, options=0,
                 split_dims=0, loop_dims=0)
     return [dict(full, **p) for p in plans]

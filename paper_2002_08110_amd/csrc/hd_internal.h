@@ -121,9 +121,25 @@ inline bool k3mg_used(const hd_solver *s) {
   return s->quad == 1 && s->mapped() && s->plan.kernel == 1 && k3_eligible(s);
 }
 
+// The dimension-split passes (plan kernel 2, stage_split.h) cover d = 6
+// (3 x + 3 v) and d = 5 (3 x + 2 v) at degrees 4 and 5, Gauss-Lobatto
+// collocation on Cartesian cells.
+inline bool split_eligible(const hd_solver *s) {
+  return (s->n == 5 || s->n == 6) && s->quad == 0 && !s->mapped() && s->dx == 3 &&
+         (s->d == 6 || s->d == 5);
+}
+inline bool split_used(const hd_solver *s) { return s->plan.kernel == 2 && split_eligible(s); }
+
 // Grid, workgroup size and dynamic LDS of one stage launch under the
-// solver's plan.
+// solver's plan (for plan kernel 2 its first pass).
 hd::LaunchShape shape_of(const hd_solver *s);
+
+// Entries and launch shapes of the two passes of plan kernel 2.
+struct SplitShapes {
+  hd::SplitEntry e;
+  hd::LaunchShape x, v;
+};
+SplitShapes split_shapes(const hd_solver *s);
 
 // The stage kernel of the solver's plan; k3_role selects the 6D degree-3
 // kernel's variant (0 general, 1 first stage, 2 late increment); list != 0
@@ -134,9 +150,10 @@ const void *stage_entry(const hd_solver *s, int k3_role = 0, int list = 0);
 // The stages of s run the generic kernel or the 6D degree-3 collocation
 // kernel on Cartesian cells with a prescribed field: kernels with a
 // work-list form. (The Gauss-Legendre and mapped-cell kernels take a second
-// table argument, and the Vlasov-Poisson field adds per-solve launches.)
+// table argument, the Vlasov-Poisson field adds per-solve launches, and the
+// dimension-split plan takes two launches per stage.)
 inline bool list_capable(const hd_solver *s) {
-  return s->quad == 0 && !s->mapped() && s->field_kind != 2;
+  return s->quad == 0 && !s->mapped() && s->field_kind != 2 && s->plan.kernel != 2;
 }
 
 // Kernel parameters, launch shape and 6D degree-3 role of one operator

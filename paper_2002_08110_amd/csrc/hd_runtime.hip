@@ -50,6 +50,10 @@ namespace {
 using hd::rt::fail;
 using hd::rt::fill_params;
 using hd::rt::k3_eligible;
+using hd::rt::split_eligible;
+using hd::rt::split_shapes;
+using hd::rt::split_used;
+using hd::rt::SplitShapes;
 using hd::rt::kRkA;
 using hd::rt::kRkB;
 
@@ -73,13 +77,21 @@ bool valid_plan(const hd_solver *s, const hd_plan &p, std::string *why) {
     *why = "options is a 2-bit mask";
     return false;
   }
-  if (p.kernel != 0 && p.kernel != 1) {
-    *why = "kernel must be 0 (generic) or 1 (6D degree-3)";
+  if (p.kernel < 0 || p.kernel > 2) {
+    *why = "kernel must be 0 (generic), 1 (6D degree-3) or 2 (dimension-split)";
     return false;
   }
   if (p.kernel == 1) {
     if (!k3_eligible(s)) {
       *why = "kernel 1 needs d = 6 (3 x + 3 v) and degree 3";
+      return false;
+    }
+    return true;
+  }
+  if (p.kernel == 2) {
+    if (!split_eligible(s)) {
+      *why = "kernel 2 needs d = 6 (3 x + 3 v) or d = 5 (3 x + 2 v) at degree 4 or 5, "
+             "collocation on Cartesian cells";
       return false;
     }
     return true;
@@ -225,6 +237,7 @@ hd::LaunchShape hd::rt::shape_of(const hd_solver *s) {
     ls.shmem = s->prec == HD_FP32_OP_FP64_ACC ? hd::k3_lds_bytes<float>() : hd::k3_lds_bytes<double>();
     return ls;
   }
+  if (s->plan.kernel == 2) return hd::rt::split_shapes(s).x;
   const int sd = s->plan.split_dims;
   int64_t T = 1, per_cell = 1;  // threads per unit, units per cell
   for (int j = 0; j < s->d - s->plan.reg_dims - sd - s->plan.loop_dims; ++j) T *= s->n;
@@ -244,6 +257,22 @@ hd::LaunchShape hd::rt::shape_of(const hd_solver *s) {
   return ls;
 }
 
+hd::rt::SplitShapes hd::rt::split_shapes(const hd_solver *s) {
+  SplitShapes sh{};
+  sh.e = hd::stage_split_entry(s->d, s->dx, s->n, s->prec == HD_FP32_OP_FP64_ACC, s->plan.options);
+  if (!sh.e.fx) return sh;
+  int64_t nvb = 1;
+  for (int j = 0; j < s->dv; ++j) nvb *= s->n;
+  const int64_t rows = s->ncells * nvb;
+  sh.x.grid = (unsigned)((rows + sh.e.rows_per_tile - 1) / sh.e.rows_per_tile);
+  sh.x.block = sh.e.threads_x;
+  sh.x.shmem = sh.e.lds_x;
+  sh.v.grid = (unsigned)(s->ncells * sh.e.tiles_per_cell);
+  sh.v.block = sh.e.threads_v;
+  sh.v.shmem = sh.e.lds_v;
+  return sh;
+}
+
 namespace hd {
 namespace rt {
 
@@ -256,6 +285,10 @@ const void *stage_entry(const hd_solver *s, int k3_role, int list) {
   if (s->quad == 1 || s->mapped()) return hd::stage_gauss_entry(s->d, s->n, f32, s->mapped());
   if (s->plan.kernel == 1) return f32 ? hd::stage_k3_f32(s->plan.options, k3_role, list)
                                       : hd::stage_k3_f64(s->plan.options, k3_role, list);
+  if (s->plan.kernel == 2) {
+    if (list) return nullptr;
+    return hd::stage_split_entry(s->d, s->dx, s->n, f32, s->plan.options).fx;
+  }
   const int rd = s->plan.reg_dims, lds = s->plan.lds, n = s->n, sd = s->plan.split_dims,
             opt = s->plan.options, ld = s->plan.loop_dims;
   switch (s->d) {
@@ -487,6 +520,20 @@ hd_status launch_op(hd_solver *s, const double *in, void *out, double *u_out, in
       }
     }
     if (s->mapped()) prm.xmetric = s->xmetric();
+  }
+  if (split_used(s)) {
+    // Pass x, then pass v (stage_split.h), each with its own grid.
+    const SplitShapes sh = split_shapes(s);
+    if ((uint64_t)sh.v.grid * sh.v.block >= (uint64_t(1) << 32))
+      return fail(HD_ERR_UNSUPPORTED, "stage launch exceeds 2^32 work-items");
+    prm.nblocks = sh.x.grid;
+    hipError_t e = hipLaunchKernel(sh.e.fx, dim3(sh.x.grid), dim3(sh.x.block), args, sh.x.shmem, st);
+    if (e == hipSuccess) {
+      prm.nblocks = sh.v.grid;
+      e = hipLaunchKernel(sh.e.fv, dim3(sh.v.grid), dim3(sh.v.block), args, sh.v.shmem, st);
+    }
+    if (e != hipSuccess) return fail(HD_ERR_HIP, std::string("stage kernel launch: ") + hipGetErrorString(e));
+    return HD_OK;
   }
   hipError_t e = hipLaunchKernel(fn, dim3(ls.grid), dim3(ls.block), args, ls.shmem, st);
   if (e != hipSuccess) return fail(HD_ERR_HIP, std::string("stage kernel launch: ") + hipGetErrorString(e));

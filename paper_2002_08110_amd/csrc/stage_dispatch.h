@@ -158,4 +158,19 @@ const void *stage_k3mg_entry(bool f32);
 // nullptr where the cell's LDS does not fit.
 const void *stage_gauss_entry(int d, int n, bool f32, bool mapped = false);
 
+// Dimension-split passes (stage_split.hip): pass x over tiles of
+// rows_per_tile consecutive rows (the n^dx x-nodes of one velocity node
+// tuple of a cell), threads_x threads and lds_x bytes of LDS; pass v over
+// tiles_per_cell column blocks of each cell (cols_per_tile x-nodes in every
+// row), threads_v threads and lds_v bytes. Compiled for d = 6 (3 + 3) and d = 5
+// (3 + 2) at degrees 4 and 5 with Gauss-Lobatto collocation on Cartesian
+// cells; null entries otherwise. options as in hd_plan (bit 0).
+struct SplitEntry {
+  const void *fx = nullptr, *fv = nullptr;
+  int rows_per_tile = 0, cols_per_tile = 0, tiles_per_cell = 0;
+  unsigned threads_x = 0, threads_v = 0;
+  size_t lds_x = 0, lds_v = 0;
+};
+SplitEntry stage_split_entry(int d, int dx, int n, bool f32, int options);
+
 }  // namespace hd

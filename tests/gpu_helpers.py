@@ -113,6 +113,22 @@ def all_plans(case: W.Case, precision="fp64"):
     return [dict(full, **p) for p in plans]
 
 
+def split_eligible(case: W.Case):
+    """The dimension-split passes (plan kernel 2): 6D (3 x + 3 v) or 5D
+    (3 x + 2 v) at degree 4 or 5, collocation on Cartesian cells."""
+    return case.dim_x == 3 and case.dim_v in (2, 3) and case.degree in (4, 5)
+
+
+def split_plans(case: W.Case):
+    """Every launch plan of the dimension-split passes: both cell orders,
+    with and without streaming stores."""
+    if not split_eligible(case):
+        return []
+    full = dict(lds=0, cells_per_wg=1, wg_size=256, xcd_remap=0, reg_dims=1, kernel=2, options=0,
+                split_dims=0, loop_dims=0)
+    return [dict(full, xcd_remap=x, options=o) for x in (0, 1) for o in (0, 1)]
+
+
 def k3_eligible(case: W.Case):
     """The specialised kernel: 6D (3 x + 3 v), degree 3, < 2^31 DoFs."""
     return case.dim_x == 3 and case.dim_v == 3 and case.degree == 3 and case.ndofs < 2 ** 31

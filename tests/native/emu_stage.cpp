@@ -4,7 +4,7 @@
 // buffer and every LDS access inside the launch's dynamic LDS. Built by
 // tests/test_kernel_emulation_cpu.py with one kernel variant chosen at
 // compile time (EMU_D, EMU_N, EMU_DX, EMU_RD, EMU_P, EMU_LDS, EMU_SD,
-// EMU_OPT, EMU_LD).
+// EMU_OPT, EMU_LD; EMU_SPLIT: the two dimension-split passes instead).
 //
 // Usage: emu_stage DIR  with DIR/spec.txt holding
 //   cells (d values)  lo (d)  hi (d)  field_kind  a (d) or esign
@@ -30,6 +30,7 @@
 
 #include "hd_internal.h"
 #include "stage_k3.h"
+#include "stage_split.h"
 #include "work_list.h"
 
 thread_local emu_dim3 threadIdx, blockIdx;
@@ -196,6 +197,58 @@ int emu_mov_dpp(int v, int ctrl) {
   return r;
 }
 
+#ifdef EMU_SPLIT
+// The dimension-split passes (plan kernel 2): pass x, then pass v, on one
+// set of buffers, with the library's launch shapes.
+template <typename P, int D, int N, int DX>
+int run_split(hd_solver &s, const std::string &dir, int mode, int stage, double dt, double rk_a,
+              double rk_b, int xcd, size_t nE) {
+  using S = hd::SplitShape<D, N, DX>;
+  const size_t nd = (size_t)s.ndofs;
+  const std::vector<double> u = read_bin<double>(dir + "/u.bin", nd);
+  std::vector<P> du = read_bin<P>(dir + "/du.bin", nd);
+  std::vector<P> E(std::max<size_t>(nE, 1), P(0));
+  if (s.field_kind == 1) E = read_bin<P>(dir + "/E.bin", nE);
+  std::vector<double> uo(nd, -7.0);
+  std::vector<P> out(nd, P(-7));
+  hd::StageParams<P> prm;
+  hd::rt::fill_params<P>(&s, &prm, 0);
+  prm.xcd_remap = xcd;
+  prm.E = E.data();
+  prm.u_in = u.data();
+  prm.mode = mode;
+  prm.du = du.data();
+  if (mode == 0) {
+    prm.out = out.data();
+  } else {
+    prm.u_out = uo.data();
+    prm.read_du = stage > 0;
+    prm.write_du = stage < 4;
+    prm.rk_a = (P)rk_a;
+    prm.rk_b = rk_b;
+    prm.dt = (P)dt;
+  }
+  const uint64_t rows = (uint64_t)s.ncells * S::NVB;
+  const unsigned gx = (unsigned)((rows + S::R - 1) / S::R);
+  const unsigned gv = (unsigned)(s.ncells * S::NCH);
+  const size_t lx = hd::split_x_lds_bytes<D, N, DX, P>(), lv = hd::split_v_lds_bytes<D, N, DX, P>();
+  prm.nblocks = gx;
+  const hd::StageParams<P> px = prm;
+  run_grid(gx, S::TX, lx, [&] { hd::stage_split_x_kernel<D, N, DX, P, EMU_OPT>(px); });
+  prm.nblocks = gv;
+  const hd::StageParams<P> pv = prm;
+  run_grid(gv, S::TV, lv, [&] { hd::stage_split_v_kernel<D, N, DX, P, EMU_OPT>(pv); });
+  if (mode == 0) {
+    write_bin(dir + "/out.bin", out.data(), nd);
+  } else {
+    write_bin(dir + "/out_u.bin", uo.data(), nd);
+    write_bin(dir + "/out_du.bin", du.data(), nd);
+  }
+  std::printf("split: pass x grid %u lds %zu, pass v grid %u lds %zu\n", gx, lx, gv, lv);
+  return 0;
+}
+#endif
+
 int main(int argc, char **argv) {
   using P = EMU_P;
   constexpr int D = EMU_D, N = EMU_N, DX = EMU_DX, RD = EMU_RD, SD = EMU_SD, LD = EMU_LD;
@@ -254,6 +307,10 @@ int main(int argc, char **argv) {
   constexpr bool K3 = false;
 #endif
   s.plan.kernel = K3 ? 1 : 0;
+#ifdef EMU_SPLIT
+  s.plan.kernel = 2;
+  return run_split<P, D, N, DX>(s, dir, mode, stage, dt, rk_a, rk_b, xcd, nE);
+#endif
   // Launch shape of the generic kernel under this plan (as the library's).
   int64_t T = 1, per_cell = 1;
   for (int j = 0; j < D - RD - SD - LD; ++j) T *= N;
