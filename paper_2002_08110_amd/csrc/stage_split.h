@@ -99,11 +99,30 @@ __device__ __forceinline__ unsigned split_drop_digit(unsigned q) {
   return (q % st) + (q / (st * N)) * st;
 }
 
-// Multi-index of a cell (x dims first, dimension 1 fastest).
+// Multi-index of a cell (x dims first, dimension 1 fastest): one division
+// per dimension, peeling the digits from the fastest.
 template <int D, typename PV>
 __device__ __forceinline__ void split_cell_index(PV &prm, unsigned cell, unsigned *c) {
+  unsigned t = cell;
 #pragma unroll
-  for (int j = 0; j < D; ++j) c[j] = (cell / prm.cstride[j]) % prm.cells[j];
+  for (int j = 0; j < D; ++j) {
+    const unsigned q = j + 1 < D ? t / prm.cells[j] : 0u;
+    c[j] = j + 1 < D ? t - q * prm.cells[j] : t;
+    t = q;
+  }
+}
+
+// Multi-index of cell + 1 from that of cell (digits carried; for the last
+// cell the result wraps to cell 0, and no caller uses it then).
+template <int D, typename PV>
+__device__ __forceinline__ void split_next_index(PV &prm, const unsigned *c, unsigned *n) {
+  bool carry = true;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    const bool wrap = carry && c[j] + 1 == prm.cells[j];
+    n[j] = carry ? (wrap ? 0u : c[j] + 1) : c[j];
+    carry = wrap;
+  }
 }
 
 // Periodic neighbour of `cell` (multi-index c) along dimension J: the left
@@ -181,7 +200,7 @@ __global__ void __launch_bounds__((SplitShape<D, N, DX>::TX)) stage_split_x_kern
   const unsigned c1 = c0 + 1 < prm.ncells ? c0 + 1 : c0;
   unsigned ci0[D], ci1[D], ci[D];
   split_cell_index<D>(prm, c0, ci0);
-  split_cell_index<D>(prm, c1, ci1);
+  split_next_index<D>(prm, ci0, ci1);  // used only by rows of c1, which exist if c0 + 1 < ncells
   const bool cs = vt0 + r >= (unsigned)NVB;
   const unsigned vt = cs ? vt0 + r - NVB : vt0 + r;
   const unsigned cell = cs ? c1 : c0;
