@@ -258,9 +258,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
     const P f10 = (P)mf1[0], f11 = (P)mf1[1], f12 = (P)mf1[2];
     const P a0 = (P)mg[l * MXE + 3 * j], a1 = (P)mg[l * MXE + 3 * j + 1], a2 = (P)mg[l * MXE + 3 * j + 2];
     const P e0 = tExt[ij], e1 = tExt[4 + ij], lf0 = tLift[ij], lf1 = tLift[4 + ij];
-    P p[16];
+    // Four register values at a time (the lane transform acts on each value
+    // by itself): only four volume terms are live beside z and Ux.
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
+    for (int c4 = 0; c4 < 4; ++c4) {
+    P p[4];
+#pragma unroll
+    for (int si = 0; si < 4; ++si) {
+      const int s = 4 * c4 + si;
       const int i5 = s & 3, i6 = s >> 2;
       P g2 = P(0), g3 = P(0);
 #pragma unroll
@@ -271,7 +276,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
       const P V1s = uxb[t + 256 * s];
       const P V2 = alpha[1] * ux[s] + vhh[1] * g2;
       const P V3 = alpha[2] * ux[s] + vhh[2] * g3;
-      p[s] = a0 * V1s + a1 * V2 + a2 * V3;
+      p[si] = a0 * V1s + a1 * V2 + a2 * V3;
       P w0 = e0 * (f00 * V1s + f01 * V2 + f02 * V3);
       P w1 = e1 * (f10 * V1s + f11 * V2 + f12 * V3);
       if (j == 0) {
@@ -287,11 +292,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
       // - lift_s (ahat.n) u_own, n_0 = -1, n_1 = +1
       z[s] += lf0 * w0 - lf1 * w1;
     }
-    if (j == 0) k3g_lane<1, 16>(tDw, p, l);
-    else if (j == 1) k3g_lane<2, 16>(tDw, p, l);
-    else k3g_lane<3, 16>(tDw, p, l);
+    if (j == 0) k3g_lane<1, 4>(tDw, p, l);
+    else if (j == 1) k3g_lane<2, 4>(tDw, p, l);
+    else k3g_lane<3, 4>(tDw, p, l);
 #pragma unroll
-    for (int s = 0; s < 16; ++s) z[s] += p[s];
+    for (int si = 0; si < 4; ++si) z[4 * c4 + si] += p[si];
+    }
   }
 
   // ---- faces of the v-dimensions: upwind jumps (Cartesian form), scaled by |J| ----
