@@ -22,6 +22,7 @@
 #define __launch_bounds__(...)
 #define amdgpu_waves_per_eu(...)
 #define __shared__
+#define __align__(n) __attribute__((aligned(n)))
 
 struct emu_dim3 {
   unsigned x = 0, y = 0, z = 0;
@@ -35,6 +36,7 @@ int emu_mov_dpp(int v, int ctrl);
 #define __builtin_amdgcn_mov_dpp(v, ctrl, row_mask, bank_mask, bound_ctrl) emu_mov_dpp((v), (ctrl))
 #define __builtin_amdgcn_sched_barrier(x) ((void)0)
 #define __builtin_amdgcn_readfirstlane(x) (x)
+inline int atomicOr(int *p, int v) { return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST); }
 
 typedef void *hipStream_t;
 typedef void *hipGraphExec_t;
