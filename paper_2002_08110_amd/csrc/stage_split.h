@@ -273,7 +273,6 @@ __global__ void __launch_bounds__((SplitShape<D, N, DX>::TX)) stage_split_x_kern
     for (int i = 0; i < N; ++i) lu[r * RS + lbase + i] = to_p<P>(u64[i]);
   }
   __syncthreads();
-  if (!active) return;
 
   P up[N], acc[N], sum[N];
 #pragma unroll
@@ -281,6 +280,7 @@ __global__ void __launch_bounds__((SplitShape<D, N, DX>::TX)) stage_split_x_kern
     up[i] = to_p<P>(u64[i]);
     acc[i] = P(0);
   }
+  if (active) {
   // Dimension 1 on the thread's registers.
   split_own_sweep<N>(prm, up, sum);
   {
@@ -321,18 +321,34 @@ __global__ void __launch_bounds__((SplitShape<D, N, DX>::TX)) stage_split_x_kern
   };
   if constexpr (DX > 1) sweep(std::integral_constant<int, 1>{});
   if constexpr (DX > 2) sweep(std::integral_constant<int, 2>{});
-
-  const uint64_t g = rbase + lbase;
+  // The result: the x-sum, or (FP32 stage) the increment with A du folded in.
+  if constexpr (F32) {
+    if (stage) {
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
-    if (!stage) {
-      prm.out[g + i] = acc[i];
-    } else if constexpr (F32) {
-      const P d = prm.read_du ? rk_fma(prm.rk_a, dv[i], prm.dt * acc[i]) : prm.dt * acc[i];
-      st_opt<NT>(prm.du + g + i, d);
-    } else {
-      st_opt<NT>(prm.u_out + g + i, (double)acc[i]);
+      for (int i = 0; i < N; ++i)
+        acc[i] = prm.read_du ? rk_fma(prm.rk_a, dv[i], prm.dt * acc[i]) : prm.dt * acc[i];
     }
+  }
+  }  // active
+
+  // Out through the LDS rows (once every thread has read them for its
+  // sweeps): the tile's rows are contiguous in memory, and consecutive lanes
+  // then store consecutive values (a thread's own line would leave every
+  // 64-byte sector to three partial stores).
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) lu[r * RS + lbase + i] = acc[i];
+  }
+  __syncthreads();
+  const uint64_t base = g0 * NXB;
+  const unsigned tn = nr * NXB;
+  for (unsigned n = tid; n < tn; n += S::TX) {
+    const unsigned rr = n / NXB, x = n - rr * NXB;
+    const P v = lu[rr * RS + x];
+    if (!stage) prm.out[base + n] = v;
+    else if constexpr (F32) st_opt<NT>(prm.du + base + n, v);
+    else st_opt<NT>(prm.u_out + base + n, (double)v);
   }
 }
 
