@@ -70,15 +70,15 @@ struct SplitShape {
   // addresses.
   static constexpr int RS = NXB + 2;
   static constexpr int CS = C + 1;
-  // LDS tables: Dm[N][N] and the nodes xi[N], read with per-lane indices (a
-  // kernel argument indexed at run time would be copied to scratch memory).
-  static constexpr int NTAB = N * N + N;
+  // LDS table Dm[N][N], read with per-lane row indices (a kernel argument
+  // indexed at run time would be copied to scratch memory).
+  static constexpr int NTAB = N * N;
   static_assert(R >= 1 && R <= NVB, "a pass-x tile spans at most two cells");
   static_assert(C >= 1 && C <= NXB, "a column block lies in one cell");
 };
 
-// LDS of pass x: tables, the rows, the inflow-face lines of x dims 2..dx
-// (per row and dim, the LX / N lines of the face); of pass v: tables, the
+// LDS of pass x: the table, the rows, the inflow-face lines of x dims 2..dx
+// (per row and dim, the LX / N lines of the face); of pass v: the table, the
 // column block, the face lines of velocity dims 2..dv (per dim, LV / N lines
 // of N values, each by column).
 template <int D, int N, int DX, typename P>
@@ -145,15 +145,13 @@ __device__ __forceinline__ unsigned split_set_digit(unsigned q, unsigned dig) {
   return q + (dig - split_digit<N, J>(q)) * st;
 }
 
-// The tables Dm and xi into LDS (one thread; compile-time indices), for
-// reads after the workgroup's barrier.
+// The table Dm into LDS (one thread; compile-time indices), for reads after
+// the workgroup's barrier.
 template <int N, typename PV, typename P>
 __device__ __forceinline__ void split_tables(PV &prm, P *tab) {
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int q = 0; q < N * N; ++q) tab[q] = prm.Dm[q];
-#pragma unroll
-    for (int q = 0; q < N; ++q) tab[N * N + q] = prm.xi[q];
   }
 }
 
@@ -180,7 +178,7 @@ __global__ void __launch_bounds__((SplitShape<D, N, DX>::TX)) stage_split_x_kern
   constexpr bool NT = (OPT & kOptStream) != 0;
   constexpr bool F32 = sizeof(P) == 4;
   extern __shared__ unsigned char smem_raw[];
-  P *tab = reinterpret_cast<P *>(smem_raw);  // Dm, xi
+  P *tab = reinterpret_cast<P *>(smem_raw);  // Dm
   P *lu = tab + S::NTAB;                     // [R][RS] the rows
   P *lf = lu + R * RS;                       // [R][DX-1][LX/N][N] face lines
   const unsigned tid = threadIdx.x;
@@ -220,6 +218,7 @@ __global__ void __launch_bounds__((SplitShape<D, N, DX>::TX)) stage_split_x_kern
     } else {
       const int m = DX + j < D ? DX + j : D - 1;
       const unsigned dig = (vt / (unsigned)ipow(N, j)) % N;
+      // xi[dig] by a chain of selects over the kernel argument
       P xi = prm.xi[0];
 #pragma unroll
       for (int q = 1; q < N; ++q) xi = dig == (unsigned)q ? prm.xi[q] : xi;
@@ -228,7 +227,7 @@ __global__ void __launch_bounds__((SplitShape<D, N, DX>::TX)) stage_split_x_kern
   }
 
   // The line, the inflow traces and (FP32 stage) the increment.
-  double u64[N];
+  double u64[N] = {};
   P fx0 = P(0);
   P dv[N];
   // Face line of x dim J (2..dx) of this thread's row, at the thread's
@@ -363,7 +362,7 @@ __global__ void __launch_bounds__((SplitShape<D, N, DX>::TV)) stage_split_v_kern
   constexpr bool NT = (OPT & kOptStream) != 0;
   constexpr bool F32 = sizeof(P) == 4;
   extern __shared__ unsigned char smem_raw[];
-  P *tab = reinterpret_cast<P *>(smem_raw);  // Dm, xi
+  P *tab = reinterpret_cast<P *>(smem_raw);  // Dm
   P *lc = tab + S::NTAB;                     // [NVB][CS] the column block
   P *lf = lc + S::NVB * CS;                  // [DV-1][LV/N][N][CS] face lines
   const unsigned tid = threadIdx.x;
