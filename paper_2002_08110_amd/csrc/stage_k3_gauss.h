@@ -216,6 +216,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
   P acc[16];
 #pragma unroll
   for (int s = 0; s < 16; ++s) acc[s] = P(0);
+  // FP64: the v-face jumps stay at the x-Gauss points, lifted along v_j
+  // (which commutes with the x-transforms) into zv, which joins the v-volume
+  // terms before their one inverse x-transform (12.5 against 13.8 ms per
+  // stage at 8^6, and no spills). FP32 transforms each jump back and lifts
+  // it in nodal form: at its three waves per SIMD the extra live zv spills
+  // (11.7 against 10.5 ms).
+  constexpr bool kMergeV = sizeof(P) == sizeof(double);
+  P zv[kMergeV ? 16 : 1];
+#pragma unroll
+  for (int s = 0; s < (kMergeV ? 16 : 1); ++s) zv[s] = P(0);
 
   // ---- faces ----
 #pragma unroll
@@ -255,9 +265,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
       const P m = a < P(0) ? a : P(0);
 #pragma unroll
       for (int q = 0; q < 4; ++q) f[q] *= m;
-      k3g_lane<3, 4>(tBinv, f, l);
-      k3g_lane<2, 4>(tBinv, f, l);
-      k3g_lane<1, 4>(tBinv, f, l);
+      if constexpr (!kMergeV) {
+        k3g_lane<3, 4>(tBinv, f, l);
+        k3g_lane<2, 4>(tBinv, f, l);
+        k3g_lane<1, 4>(tBinv, f, l);
+      }
       const P ih = prm.inv_h[j];
       const P *bl = tBl + 4 * side[j];
       if (j == 3) {
@@ -267,12 +279,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-          for (int i5 = 0; i5 < 4; ++i5) acc[i5 + 4 * q] += ih * bl[i5] * f[q];
+          for (int i5 = 0; i5 < 4; ++i5) {
+            if constexpr (kMergeV) zv[i5 + 4 * q] -= ih * bl[i5] * f[q];
+            else acc[i5 + 4 * q] += ih * bl[i5] * f[q];
+          }
       } else {
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-          for (int i6 = 0; i6 < 4; ++i6) acc[q + 4 * i6] += ih * bl[i6] * f[q];
+          for (int i6 = 0; i6 < 4; ++i6) {
+            if constexpr (kMergeV) zv[q + 4 * i6] -= ih * bl[i6] * f[q];
+            else acc[q + 4 * i6] += ih * bl[i6] * f[q];
+          }
       }
     }
     __syncthreads();
@@ -280,7 +298,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     if (side[3] >= 0) {
       const P wl = prm.inv_h[3] * tBl[4 * side[3] + w];
 #pragma unroll
-      for (int s = 0; s < 16; ++s) acc[s] += wl * faceb[3 * F + l + 64 * s];
+      for (int s = 0; s < 16; ++s) {
+        if constexpr (kMergeV) zv[s] -= wl * faceb[3 * F + l + 64 * s];
+        else acc[s] += wl * faceb[3 * F + l + 64 * s];
+      }
     }
     // x faces: Am = B^-1 diag(min(a(g) n, 0)) B along v_j, lifted along x_j
 #pragma unroll
@@ -361,57 +382,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     }
   }
 
-  // ---- volume, x-dimensions: (alpha I + vh G) along v_j, Dt along x_j ----
-  {
-    // j = 0: G along i4 (waves, from LDS), Dt along i1
-    P y[16];
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      P g4 = P(0);
-#pragma unroll
-      for (int mm = 0; mm < 4; ++mm) g4 += tG[w * 4 + mm] * cellb[l + 64 * mm + 256 * s];
-      y[s] = alpha[0] * u[s] + vhh[0] * g4;
-    }
-    k3g_lane<1, 16>(tDt, y, l);
-    const P ih = prm.inv_h[0];
-#pragma unroll
-    for (int s = 0; s < 16; ++s) acc[s] -= ih * y[s];
-  }
-  {
-    // j = 1: G along i5 (registers), Dt along i2
-    P y[16];
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const int i5 = s & 3, s0 = s - i5;
-      P g5 = P(0);
-#pragma unroll
-      for (int mm = 0; mm < 4; ++mm) g5 += gt.G[i5 * 4 + mm] * u[s0 + mm];
-      y[s] = alpha[1] * u[s] + vhh[1] * g5;
-    }
-    k3g_lane<2, 16>(tDt, y, l);
-    const P ih = prm.inv_h[1];
-#pragma unroll
-    for (int s = 0; s < 16; ++s) acc[s] -= ih * y[s];
-  }
   const int off3 = (l & 15) + 64 * w;  // the lane's line along i3 in the cell
-  {
-    // j = 2: Dt along i3 (lanes 16 apart, from LDS), then G along i6
-    const P r0 = tDt[i3 * 4], r1 = tDt[i3 * 4 + 1], r2 = tDt[i3 * 4 + 2], r3 = tDt[i3 * 4 + 3];
-    P y[16];
-#pragma unroll
-    for (int s = 0; s < 16; ++s)
-      y[s] = r0 * cellb[off3 + 256 * s] + r1 * cellb[off3 + 16 + 256 * s] +
-             r2 * cellb[off3 + 32 + 256 * s] + r3 * cellb[off3 + 48 + 256 * s];
-    const P ih = prm.inv_h[2];
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const int i6 = s >> 2, s0 = s & 3;
-      P g6 = P(0);
-#pragma unroll
-      for (int mm = 0; mm < 4; ++mm) g6 += gt.G[i6 * 4 + mm] * y[s0 + 4 * mm];
-      acc[s] -= ih * (alpha[2] * y[s] + vhh[2] * g6);
-    }
-  }
+  // The two volume parts, in the order that keeps the fewest values live:
+  // FP64 the v-terms first (zv ends there), FP32 the x-terms first.
+  auto vvolume = [&]() {
   // ---- volume, v-dimensions ----
   // B^-1(x3) [sum_j E_j(g) (Dt along v_j) Ux / h_j], Ux = B(x3) u: the
   // derivatives along v_j commute with the x-transform, which is applied once.
@@ -445,12 +419,74 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         d6 += gt.Dt[i6 * 4 + mm] * ux[i5 + 4 * mm];
       }
       z[s] = c4 * d4 + c5 * d5 + c6 * d6;
+      if constexpr (kMergeV) z[s] += zv[s];
     }
     k3g_lane<3, 16>(tBinv, z, l);
     k3g_lane<2, 16>(tBinv, z, l);
     k3g_lane<1, 16>(tBinv, z, l);
 #pragma unroll
     for (int s = 0; s < 16; ++s) acc[s] -= z[s];
+  }
+
+  };
+  auto xvolume = [&]() {
+  // ---- volume, x-dimensions: (alpha I + vh G) along v_j, Dt along x_j ----
+  {
+    // j = 0: G along i4 (waves, from LDS), Dt along i1
+    P y[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      P g4 = P(0);
+#pragma unroll
+      for (int mm = 0; mm < 4; ++mm) g4 += tG[w * 4 + mm] * cellb[l + 64 * mm + 256 * s];
+      y[s] = alpha[0] * u[s] + vhh[0] * g4;
+    }
+    k3g_lane<1, 16>(tDt, y, l);
+    const P ih = prm.inv_h[0];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) acc[s] -= ih * y[s];
+  }
+  {
+    // j = 1: G along i5 (registers), Dt along i2
+    P y[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int i5 = s & 3, s0 = s - i5;
+      P g5 = P(0);
+#pragma unroll
+      for (int mm = 0; mm < 4; ++mm) g5 += gt.G[i5 * 4 + mm] * u[s0 + mm];
+      y[s] = alpha[1] * u[s] + vhh[1] * g5;
+    }
+    k3g_lane<2, 16>(tDt, y, l);
+    const P ih = prm.inv_h[1];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) acc[s] -= ih * y[s];
+  }
+  {
+    // j = 2: Dt along i3 (lanes 16 apart, from LDS), then G along i6
+    const P r0 = tDt[i3 * 4], r1 = tDt[i3 * 4 + 1], r2 = tDt[i3 * 4 + 2], r3 = tDt[i3 * 4 + 3];
+    P y[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s)
+      y[s] = r0 * cellb[off3 + 256 * s] + r1 * cellb[off3 + 16 + 256 * s] +
+             r2 * cellb[off3 + 32 + 256 * s] + r3 * cellb[off3 + 48 + 256 * s];
+    const P ih = prm.inv_h[2];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int i6 = s >> 2, s0 = s & 3;
+      P g6 = P(0);
+#pragma unroll
+      for (int mm = 0; mm < 4; ++mm) g6 += gt.G[i6 * 4 + mm] * y[s0 + 4 * mm];
+      acc[s] -= ih * (alpha[2] * y[s] + vhh[2] * g6);
+    }
+  }
+  };
+  if constexpr (kMergeV) {
+    vvolume();
+    xvolume();
+  } else {
+    xvolume();
+    vvolume();
   }
 
   // ---- output / RK update ----
