@@ -228,7 +228,7 @@ __global__ void __launch_bounds__((SplitShape<D, N, DX>::TX)) stage_split_x_kern
 
   // The line, the inflow traces and (FP32 stage) the increment.
   double u64[N] = {};
-  P fx0 = P(0);
+  double fx0 = 0.0;
   P dv[N];
   // Face line of x dim J (2..dx) of this thread's row, at the thread's
   // position in the face.
@@ -236,18 +236,26 @@ __global__ void __launch_bounds__((SplitShape<D, N, DX>::TX)) stage_split_x_kern
     constexpr int J = decltype(Jc)::value;
     return lf + ((r * (DX - 1) + (J - 1)) * (LX / N) + split_drop_digit<N, J - 1>(l)) * N;
   };
+  // The loads go out together: the face lines into registers, to LDS once
+  // every load has been issued (a store inside each face's branch would wait
+  // for all earlier loads before the next face's loads could start).
+  double fl[DX > 1 ? DX - 1 : 1][N];
   if (active) {
 #pragma unroll
     for (int i = 0; i < N; ++i) u64[i] = prm.u_in[rbase + lbase + i];
+    if (F32 && stage && prm.read_du) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) dv[i] = ld_opt<NT>(prm.du + rbase + lbase + i);
+    }
     // Dimension 1: one trace value at the line's inflow end.
     if (a[0] != P(0)) {
       const unsigned nb = cs ? split_neighbour<0>(prm, c1, ci1, a[0] < P(0))
                              : split_neighbour<0>(prm, c0, ci0, a[0] < P(0));
       const uint64_t nrow = ((uint64_t)nb * NVB + vt) * NXB;
-      fx0 = to_p<P>(prm.u_in[nrow + lbase + (a[0] > P(0) ? N - 1 : 0)]);
+      fx0 = prm.u_in[nrow + lbase + (a[0] > P(0) ? N - 1 : 0)];
     }
     // Dimensions 2..dx: the neighbour's line, if this one lies on the
-    // inflow face, into LDS.
+    // inflow face.
     auto face = [&](auto Jc) {
       constexpr int J = decltype(Jc)::value;
       const unsigned ij = split_digit<N, J - 1>(l);
@@ -257,19 +265,35 @@ __global__ void __launch_bounds__((SplitShape<D, N, DX>::TX)) stage_split_x_kern
                                : split_neighbour<J>(prm, c0, ci0, useR);
         const uint64_t nrow = ((uint64_t)nb * NVB + vt) * NXB;
         const unsigned nl = split_set_digit<N, J - 1>(l, useL ? N - 1 : 0);
-        P *f = face_at(Jc);
 #pragma unroll
-        for (int i = 0; i < N; ++i) f[i] = to_p<P>(prm.u_in[nrow + nl * N + i]);
+        for (int i = 0; i < N; ++i) fl[J - 1][i] = prm.u_in[nrow + nl * N + i];
       }
     };
     if constexpr (DX > 1) face(std::integral_constant<int, 1>{});
     if constexpr (DX > 2) face(std::integral_constant<int, 2>{});
-    if (F32 && stage && prm.read_du) {
+    // FP32: the empty asm keeps the conversions out of the load branches
+    // (the compiler would convert right after each load, and wait for it,
+    // before the next face's loads).
+    if constexpr (F32) {
+      asm volatile("" : "+v"(fx0));
 #pragma unroll
-      for (int i = 0; i < N; ++i) dv[i] = ld_opt<NT>(prm.du + rbase + lbase + i);
+      for (int j = 0; j < (DX > 1 ? DX - 1 : 1); ++j)
+#pragma unroll
+        for (int i = 0; i < N; ++i) asm volatile("" : "+v"(fl[j][i]));
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) lu[r * RS + lbase + i] = to_p<P>(u64[i]);
+    auto face_store = [&](auto Jc) {
+      constexpr int J = decltype(Jc)::value;
+      const unsigned ij = split_digit<N, J - 1>(l);
+      if ((ij == 0 && a[J] > P(0)) || (ij == N - 1 && a[J] < P(0))) {
+        P *f = face_at(Jc);
+#pragma unroll
+        for (int i = 0; i < N; ++i) f[i] = to_p<P>(fl[J - 1][i]);
+      }
+    };
+    if constexpr (DX > 1) face_store(std::integral_constant<int, 1>{});
+    if constexpr (DX > 2) face_store(std::integral_constant<int, 2>{});
   }
   __syncthreads();
 
@@ -287,8 +311,9 @@ __global__ void __launch_bounds__((SplitShape<D, N, DX>::TX)) stage_split_x_kern
 #pragma unroll
     for (int i = 0; i < N; ++i) acc[i] -= c * sum[i];
     const P lf0 = prm.lift_inv_h[0];
-    if (a[0] > P(0)) acc[0] += lf0 * a[0] * (fx0 - up[0]);
-    if (a[0] < P(0)) acc[N - 1] += -lf0 * a[0] * (fx0 - up[N - 1]);
+    const P f0 = to_p<P>(fx0);
+    if (a[0] > P(0)) acc[0] += lf0 * a[0] * (f0 - up[0]);
+    if (a[0] < P(0)) acc[N - 1] += -lf0 * a[0] * (f0 - up[N - 1]);
   }
   // Dimensions 2..dx: the lines through the thread's nodes from LDS, with
   // the thread's row of Dm.
@@ -385,45 +410,75 @@ __global__ void __launch_bounds__((SplitShape<D, N, DX>::TV)) stage_split_v_kern
   // Node i of the thread's line: velocity node tuple i + N q.
   auto at = [&](unsigned qq, int i) -> uint64_t { return cbase + (uint64_t)(i + N * qq) * NXB; };
 
-  // Speeds of the velocity dims at the column's x-node: esign E (phase-space
-  // field) or the constants.
-  P a[DV];
-  const bool phase = prm.field_kind == 1;
-  double u64[N];
-  P fv0 = P(0);
-  P part[N], dv[N];
   // Node i of the face line of velocity dim JJ (2..dv) at this thread's
   // position in the face.
   auto face_at = [&](auto Jc, int i) -> P & {
     constexpr int JJ = decltype(Jc)::value;
     return lf[(((JJ - 1) * (LV / N) + split_drop_digit<N, JJ - 1>(q)) * N + i) * CS + xc];
   };
+  // The loads are written without branches inside unrolled loops (uniform
+  // choices select a pointer) so that they form one block: every load that
+  // does not depend on the field is in flight while the field arrives, and
+  // the inflow-face loads that do depend on it go out together.
+  P a[DV];
+  const bool phase = prm.field_kind == 1;
+  double u64[N];
+  double fv0 = 0.0;
+  P part[N], dv[N];
+  double fl[DV > 1 ? DV - 1 : 1][N];
   if (active) {
+    // FP64 stage increment (stages after the first): its own uniform branch,
+    // ahead of the rest.
+    if constexpr (!F32) {
 #pragma unroll
-    for (int jj = 0; jj < DV; ++jj)
-      a[jj] = phase ? prm.esign * prm.E[((uint64_t)xcell * NXB + x0 + xc) * DX + jj]
-                    : prm.a_const[DX + jj];
+      for (int i = 0; i < N; ++i) dv[i] = P(0);
+      if (stage && prm.read_du) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) u64[i] = prm.u_in[at(q, i)];
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      part[i] = P(0);
-      dv[i] = P(0);
-      if (!stage) {
-        part[i] = prm.out[at(q, i)];
-      } else {
-        if constexpr (!F32) part[i] = (P)ld_opt<NT>(prm.u_out + at(q, i));
-        if (F32 || prm.read_du) dv[i] = ld_opt<NT>(prm.du + at(q, i));
+        for (int i = 0; i < N; ++i) dv[i] = ld_opt<NT>(prm.du + at(q, i));
       }
     }
+    // Speeds of the velocity dims at the column's x-node: esign E
+    // (phase-space field) or the constants. Without the field the load reads
+    // the solution's first value, a valid address, and is discarded.
+    const P *eb = phase ? prm.E + ((uint64_t)xcell * NXB + x0 + xc) * DX
+                        : reinterpret_cast<const P *>(prm.u_in);
+    P er[DV];
+#pragma unroll
+    for (int jj = 0; jj < DV; ++jj) er[jj] = eb[phase ? jj : 0];
+#pragma unroll
+    for (int i = 0; i < N; ++i) u64[i] = prm.u_in[at(q, i)];
+    // The x-sum (FP64 stage: the output solution; operator application: the
+    // output) or, in FP32 operator mode, the increment that holds it.
+    {
+      const P *ps;
+      if constexpr (F32) ps = stage ? prm.du : prm.out;
+      else ps = stage ? reinterpret_cast<const P *>(prm.u_out) : prm.out;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const P v = ld_opt<NT>(ps + at(q, i));
+        if constexpr (F32) {
+          part[i] = stage ? P(0) : v;
+          dv[i] = stage ? v : P(0);
+        } else {
+          part[i] = v;
+        }
+      }
+    }
+    // The field values are first used here, behind the loads above: the
+    // empty asm keeps the compiler from moving their loads into the branch
+    // of the phase-space field, where each would wait for all the others.
+#pragma unroll
+    for (int jj = 0; jj < DV; ++jj) asm volatile("" : "+v"(er[jj]));
+#pragma unroll
+    for (int jj = 0; jj < DV; ++jj) a[jj] = phase ? prm.esign * er[jj] : prm.a_const[DX + jj];
     // First velocity dim: one trace value at the line's inflow end.
     if (a[0] != P(0)) {
       const unsigned nb = split_neighbour<DX>(prm, cell, ci, a[0] < P(0));
       const uint64_t nbase = (uint64_t)nb * S::ND + x0 + xc;
-      fv0 = to_p<P>(prm.u_in[nbase + (uint64_t)((a[0] > P(0) ? N - 1 : 0) + N * q) * NXB]);
+      fv0 = prm.u_in[nbase + (uint64_t)((a[0] > P(0) ? N - 1 : 0) + N * q) * NXB];
     }
     // Velocity dims 2..dv: the neighbour's line, if this one lies on the
-    // inflow face, into LDS.
+    // inflow face, into registers (to LDS below, once every load is out).
     auto face = [&](auto Jc) {
       constexpr int JJ = decltype(Jc)::value;
       const unsigned ij = split_digit<N, JJ - 1>(q);
@@ -433,13 +488,30 @@ __global__ void __launch_bounds__((SplitShape<D, N, DX>::TV)) stage_split_v_kern
         const uint64_t nbase = (uint64_t)nb * S::ND + x0 + xc;
         const unsigned nq = split_set_digit<N, JJ - 1>(q, useL ? N - 1 : 0);
 #pragma unroll
-        for (int i = 0; i < N; ++i) face_at(Jc, i) = to_p<P>(prm.u_in[nbase + (uint64_t)(i + N * nq) * NXB]);
+        for (int i = 0; i < N; ++i) fl[JJ - 1][i] = prm.u_in[nbase + (uint64_t)(i + N * nq) * NXB];
       }
     };
     if constexpr (DV > 1) face(std::integral_constant<int, 1>{});
     if constexpr (DV > 2) face(std::integral_constant<int, 2>{});
+    if constexpr (F32) {
+      asm volatile("" : "+v"(fv0));
+#pragma unroll
+      for (int j = 0; j < (DV > 1 ? DV - 1 : 1); ++j)
+#pragma unroll
+        for (int i = 0; i < N; ++i) asm volatile("" : "+v"(fl[j][i]));
+    }
 #pragma unroll
     for (int i = 0; i < N; ++i) lc[(N * q + i) * CS + xc] = to_p<P>(u64[i]);
+    auto face_store = [&](auto Jc) {
+      constexpr int JJ = decltype(Jc)::value;
+      const unsigned ij = split_digit<N, JJ - 1>(q);
+      if ((ij == 0 && a[JJ] > P(0)) || (ij == N - 1 && a[JJ] < P(0))) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) face_at(Jc, i) = to_p<P>(fl[JJ - 1][i]);
+      }
+    };
+    if constexpr (DV > 1) face_store(std::integral_constant<int, 1>{});
+    if constexpr (DV > 2) face_store(std::integral_constant<int, 2>{});
   }
   __syncthreads();
   if (!active) return;
@@ -457,8 +529,9 @@ __global__ void __launch_bounds__((SplitShape<D, N, DX>::TV)) stage_split_v_kern
 #pragma unroll
     for (int i = 0; i < N; ++i) acc[i] -= c * sum[i];
     const P lf0 = prm.lift_inv_h[DX];
-    if (a[0] > P(0)) acc[0] += lf0 * a[0] * (fv0 - up[0]);
-    if (a[0] < P(0)) acc[N - 1] += -lf0 * a[0] * (fv0 - up[N - 1]);
+    const P f0 = to_p<P>(fv0);
+    if (a[0] > P(0)) acc[0] += lf0 * a[0] * (f0 - up[0]);
+    if (a[0] < P(0)) acc[N - 1] += -lf0 * a[0] * (f0 - up[N - 1]);
   }
   auto sweep = [&](auto Jc) {
     constexpr int JJ = decltype(Jc)::value;
@@ -488,19 +561,23 @@ __global__ void __launch_bounds__((SplitShape<D, N, DX>::TV)) stage_split_v_kern
   if constexpr (DV > 1) sweep(std::integral_constant<int, 1>{});
   if constexpr (DV > 2) sweep(std::integral_constant<int, 2>{});
 
+  if (!stage) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) prm.out[at(q, i)] = acc[i];
+    return;
+  }
+  P d[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    const uint64_t g = at(q, i);
-    if (!stage) {
-      prm.out[g] = acc[i];
-      continue;
-    }
-    P d;
-    if constexpr (F32) d = rk_fma(prm.dt, acc[i], dv[i]);
-    else d = prm.read_du ? rk_fma(prm.rk_a, dv[i], prm.dt * acc[i]) : prm.dt * acc[i];
-    if (prm.write_du) st_opt<NT>(prm.du + g, d);
-    st_opt<NT>(prm.u_out + g, rk_fma(prm.rk_b, (double)d, u64[i]));
+    if constexpr (F32) d[i] = rk_fma(prm.dt, acc[i], dv[i]);
+    else d[i] = prm.read_du ? rk_fma(prm.rk_a, dv[i], prm.dt * acc[i]) : prm.dt * acc[i];
   }
+  if (prm.write_du) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) st_opt<NT>(prm.du + at(q, i), d[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) st_opt<NT>(prm.u_out + at(q, i), rk_fma(prm.rk_b, (double)d[i], u64[i]));
 }
 
 }  // namespace hd
