@@ -47,10 +47,15 @@
 namespace hd {
 
 // Tile shapes of the dimension-split passes for d dims, n = N nodes per
-// dimension and dx configuration dimensions. A thread owns one line of N
-// nodes: in pass x a line along x dimension 1 of one row, in pass v a line
-// along the first velocity dimension of one column.
-template <int D, int N, int DX>
+// dimension, dx configuration dimensions and operator values of PS bytes. A
+// thread owns one line of N nodes: in pass x a line along x dimension 1 of
+// one row, in pass v a line along the first velocity dimension of one column.
+// Pass v takes as many columns as fit VT threads: 448 in FP64 (12 columns at
+// degree 5, 7 waves) and 576 in FP32 operator mode (16 columns at degree 5,
+// a whole 128-byte line of the FP64 solution per row), the faster tile in
+// each precision (at 6D degree 5: 2.38 against 2.46 ms per FP64 stage with
+// 576, 1.75 against 1.86 ms per FP32 stage with 448).
+template <int D, int N, int DX, int PS>
 struct SplitShape {
   static constexpr int DV = D - DX;
   static constexpr int NXB = ipow(N, DX);  // nodes of a row (x-nodes of a cell)
@@ -59,7 +64,8 @@ struct SplitShape {
   static constexpr int LX = ipow(N, DX - 1);  // lines of a row
   static constexpr int LV = ipow(N, DV - 1);  // lines of a column
   static constexpr int R = 256 / LX;          // rows per pass-x tile
-  static constexpr int C = 448 / LV < NXB ? 448 / LV : NXB;  // columns per pass-v tile
+  static constexpr int VT = PS == 4 ? 576 : 448;
+  static constexpr int C = VT / LV < NXB ? VT / LV : NXB;  // columns per pass-v tile
   static constexpr int NCH = (NXB + C - 1) / C;  // column blocks per cell
   static constexpr int TX = (R * LX + 63) / 64 * 64;  // threads of pass x
   static constexpr int TV = (C * LV + 63) / 64 * 64;  // threads of pass v
@@ -83,12 +89,12 @@ struct SplitShape {
 // of N values, each by column).
 template <int D, int N, int DX, typename P>
 constexpr size_t split_x_lds_bytes() {
-  using S = SplitShape<D, N, DX>;
+  using S = SplitShape<D, N, DX, sizeof(P)>;
   return (size_t)(S::NTAB + S::R * S::RS + S::R * (DX - 1) * S::LX) * sizeof(P);
 }
 template <int D, int N, int DX, typename P>
 constexpr size_t split_v_lds_bytes() {
-  using S = SplitShape<D, N, DX>;
+  using S = SplitShape<D, N, DX, sizeof(P)>;
   return (size_t)(S::NTAB + S::NVB * S::CS + (S::DV - 1) * S::LV * S::CS) * sizeof(P);
 }
 
@@ -172,8 +178,8 @@ __device__ __forceinline__ void split_own_sweep(PV &prm, const P *v, P *sum) {
 // line along x dimension 1 with the other x digits l = t mod LX of row
 // t / LX of the tile.
 template <int D, int N, int DX, typename P, int OPT>
-__global__ void __launch_bounds__((SplitShape<D, N, DX>::TX)) stage_split_x_kernel(const StageParams<P> prm) {
-  using S = SplitShape<D, N, DX>;
+__global__ void __launch_bounds__((SplitShape<D, N, DX, sizeof(P)>::TX)) stage_split_x_kernel(const StageParams<P> prm) {
+  using S = SplitShape<D, N, DX, sizeof(P)>;
   constexpr int NXB = S::NXB, NVB = S::NVB, R = S::R, LX = S::LX, RS = S::RS;
   constexpr bool NT = (OPT & kOptStream) != 0;
   constexpr bool F32 = sizeof(P) == 4;
@@ -381,8 +387,8 @@ __global__ void __launch_bounds__((SplitShape<D, N, DX>::TX)) stage_split_x_kern
 // line along the first velocity dimension of column x0 + t mod C with the
 // other velocity digits q = t / C.
 template <int D, int N, int DX, typename P, int OPT>
-__global__ void __launch_bounds__((SplitShape<D, N, DX>::TV)) stage_split_v_kernel(const StageParams<P> prm) {
-  using S = SplitShape<D, N, DX>;
+__global__ void __launch_bounds__((SplitShape<D, N, DX, sizeof(P)>::TV)) stage_split_v_kernel(const StageParams<P> prm) {
+  using S = SplitShape<D, N, DX, sizeof(P)>;
   constexpr int DV = S::DV, NXB = S::NXB, C = S::C, LV = S::LV, NCH = S::NCH, CS = S::CS;
   constexpr bool NT = (OPT & kOptStream) != 0;
   constexpr bool F32 = sizeof(P) == 4;

@@ -12,7 +12,7 @@ SplitEntry split_entry_of() {
   SplitEntry e;
   e.fx = reinterpret_cast<const void *>(&stage_split_x_kernel<D, N, DX, P, OPT>);
   e.fv = reinterpret_cast<const void *>(&stage_split_v_kernel<D, N, DX, P, OPT>);
-  using S = SplitShape<D, N, DX>;
+  using S = SplitShape<D, N, DX, sizeof(P)>;
   e.rows_per_tile = S::R;
   e.cols_per_tile = S::C;
   e.tiles_per_cell = S::NCH;

@@ -203,7 +203,7 @@ int emu_mov_dpp(int v, int ctrl) {
 template <typename P, int D, int N, int DX>
 int run_split(hd_solver &s, const std::string &dir, int mode, int stage, double dt, double rk_a,
               double rk_b, int xcd, size_t nE) {
-  using S = hd::SplitShape<D, N, DX>;
+  using S = hd::SplitShape<D, N, DX, sizeof(P)>;
   const size_t nd = (size_t)s.ndofs;
   const std::vector<double> u = read_bin<double>(dir + "/u.bin", nd);
   std::vector<P> du = read_bin<P>(dir + "/du.bin", nd);
