@@ -51,10 +51,10 @@ namespace hd {
 // thread owns one line of N nodes: in pass x a line along x dimension 1 of
 // one row, in pass v a line along the first velocity dimension of one column.
 // Pass v takes as many columns as fit VT threads: 448 in FP64 (12 columns at
-// degree 5, 7 waves) and 576 in FP32 operator mode (16 columns at degree 5,
-// a whole 128-byte line of the FP64 solution per row), the faster tile in
-// each precision (at 6D degree 5: 2.38 against 2.46 ms per FP64 stage with
-// 576, 1.75 against 1.86 ms per FP32 stage with 448).
+// degree 5, 7 waves) and 720 in FP32 operator mode (20 columns, 12 waves),
+// the faster tile in each precision (at 6D degree 5: 2.38 ms per FP64 stage
+// against 2.43 with 504 threads and 2.46 with 576; 1.71 ms per FP32 stage
+// against 1.75 with 576 and 1.86 with 448).
 template <int D, int N, int DX, int PS>
 struct SplitShape {
   static constexpr int DV = D - DX;
@@ -64,7 +64,7 @@ struct SplitShape {
   static constexpr int LX = ipow(N, DX - 1);  // lines of a row
   static constexpr int LV = ipow(N, DV - 1);  // lines of a column
   static constexpr int R = 256 / LX;          // rows per pass-x tile
-  static constexpr int VT = PS == 4 ? 576 : 448;
+  static constexpr int VT = PS == 4 ? 720 : 448;
   static constexpr int C = VT / LV < NXB ? VT / LV : NXB;  // columns per pass-v tile
   static constexpr int NCH = (NXB + C - 1) / C;  // column blocks per cell
   static constexpr int TX = (R * LX + 63) / 64 * 64;  // threads of pass x
