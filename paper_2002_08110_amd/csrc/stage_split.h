@@ -81,6 +81,7 @@ struct SplitShape {
   static constexpr int NTAB = N * N;
   static_assert(R >= 1 && R <= NVB, "a pass-x tile spans at most two cells");
   static_assert(C >= 1 && C <= NXB, "a column block lies in one cell");
+  static_assert(TX <= 1024 && TV <= 1024, "a workgroup holds at most 1024 threads");
 };
 
 // LDS of pass x: the table, the rows, the inflow-face lines of x dims 2..dx

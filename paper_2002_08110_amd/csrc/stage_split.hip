@@ -13,6 +13,9 @@ SplitEntry split_entry_of() {
   e.fx = reinterpret_cast<const void *>(&stage_split_x_kernel<D, N, DX, P, OPT>);
   e.fv = reinterpret_cast<const void *>(&stage_split_v_kernel<D, N, DX, P, OPT>);
   using S = SplitShape<D, N, DX, sizeof(P)>;
+  static_assert(split_x_lds_bytes<D, N, DX, P>() <= kMaxLdsBytes &&
+                    split_v_lds_bytes<D, N, DX, P>() <= kMaxLdsBytes,
+                "the tiles of both passes fit the LDS of a workgroup");
   e.rows_per_tile = S::R;
   e.cols_per_tile = S::C;
   e.tiles_per_cell = S::NCH;
